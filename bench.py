@@ -1,0 +1,178 @@
+"""Throughput of the single-copy, two-step-merged D3Q19 BGK update on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 500] [--warmup 20] [--scheme swap2] [--storage f32]
+
+Workload: 512^3 periodic lattice, FP32 (offset) storage and arithmetic,
+tau = 0.6, 3D Taylor-Green vortex (u0 = 0.02, k = 2 pi / 512) plus seeded
+uniform noise of amplitude 1e-3 per velocity component.  A "step" is one
+lattice time step; the merged scheme advances two per launch.  The fields are
+made on the host and copied in before timing; the timed region only runs
+lbm_step on device-resident data.
+
+Prints one JSON line: MLUPS over the timed region (HIP events on the stream the
+kernels run on), a roofline entry for the dominant kernel (the marching kernel,
+timed per launch by the library's event hook) against the 8 TB/s HBM peak, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+METRIC = "D3Q19 MLUPS (single-copy, two-step merged, % HBM roofline), 1 GPU"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--scheme", default="swap2", choices=["swap2", "swap1", "two_array"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    return ap.parse_args()
+
+
+def traffic_entry(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    ent = data.get(kernel_key)
+    if not ent:
+        return None
+    from paper_2208_05429_amd.build import source_digest
+    if ent.get("source_digest") != source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(target_s):
+    """The FP64 oracle (as it stands) on a bounded sample of the workload: a
+    64^3 crop-sized periodic lattice with the same tau and initial-field
+    recipe, run for as many steps as fit in about target_s seconds."""
+    import oracle
+    from paper_2208_05429_amd import workloads as wl
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    shape = (64, 64, 64)
+    rho0, u0 = wl.taylor_green_3d(shape, 0.02)
+    u0 += wl.uniform_noise(shape, 1e-3, 20805429)
+    o = oracle.Oracle(shape, 0.6)
+    f = o.init(rho0, u0)
+    t0 = time.perf_counter()
+    f = o.run(f, 2)
+    dt = (time.perf_counter() - t0) / 2
+    steps = max(2, int(target_s / max(dt, 1e-6)))
+    t0 = time.perf_counter()
+    o.run(f, steps)
+    el = time.perf_counter() - t0
+    n = int(np.prod(shape))
+    return {"value": round(n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"64^3 periodic Taylor-Green+noise, tau=0.6, {steps} steps, FP64 two-array, {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    if a.steps % 2 or a.warmup % 2:
+        print("--steps and --warmup must be even (two steps per merged pass)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2208_05429_amd import workloads as wl
+    from paper_2208_05429_amd.lattice import Lattice
+
+    shape = (a.size,) * 3
+    N = int(np.prod(shape))
+    tau = wl.TGV_512["tau"]
+    print(f"[bench] building {shape} {a.storage} {a.scheme} fields", file=sys.stderr, flush=True)
+    _, u0 = wl.tgv_512_fields(shape)
+    u0_dev = torch.from_numpy(u0).to("cuda")
+    del u0
+    lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
+    del u0_dev
+    torch.cuda.empty_cache()
+    print(f"[bench] warmup {a.warmup} steps", file=sys.stderr, flush=True)
+    lat.step(a.warmup)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lat.step(a.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms, kn = lat.kernel_time()
+    lat.set_kernel_timing(False)
+    print(f"[bench] timed {a.steps} steps in {ms:.2f} ms", file=sys.stderr, flush=True)
+    sums = lat.sums()
+    if not np.all(np.isfinite(sums)):
+        print("[bench] non-finite state after the timed run", file=sys.stderr)
+        sys.exit(3)
+
+    mlups = N * a.steps / (ms * 1e-3) / 1e6
+    M = 2 if a.scheme == "swap2" else 1
+    k = 1 if M == 2 else 0
+    avg_kernel_ms = kms[k] / max(kn[k], 1)
+    s = BYTES[a.storage]
+    alg_bytes = 2 * 19 * s * N  # one read and one write of the single copy per launch
+    achieved = alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
+    kernel_key = f"march_M{M}_{a.storage}_{a.size}" if a.scheme != "two_array" else f"two_array_{a.storage}_{a.size}"
+    traffic = traffic_entry(kernel_key)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms / a.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.storage,
+        "data": "synthetic",
+        "config": {"workload": f"{a.size}^3 periodic D3Q19 BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
+                               f"(seed 20805429), {a.storage} storage",
+                   "scheme": a.scheme, "steps_per_launch": M, "variant": a.variant,
+                   "bytes_per_lattice_update": 2 * 19 * s / M},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_march" if a.scheme != "two_array" else "k_two_array",
+                     "avg_kernel_ms": round(avg_kernel_ms, 4), "launches": kn[k],
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "conservation": {"mass": sums[0], "momentum": list(sums[1:])},
+    }
+    if not a.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * lbm.h -- C ABI of liblbm.so, an MI355X (gfx950) implementation of the
+ * memory-aware 3D lattice Boltzmann update of Fu & Song, "Designing a 3D
+ * Parallel Memory-Aware Lattice Boltzmann Algorithm on Manycore Systems":
+ * a fused D3Q19 BGK collide-and-stream done in place on a single copy of the
+ * distributions (Sec. 3, Alg. 1), with two collision-streaming steps merged
+ * per pass over memory (Sec. 4.1, Alg. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice   D3Q19.  c_0 = 0; c_1..c_9 = (-1,0,0) (0,-1,0) (0,0,-1) (-1,-1,0)
+ *           (-1,1,0) (-1,0,-1) (-1,0,1) (0,-1,-1) (0,-1,1); c_{q+9} = -c_q
+ *           (directions 1..9 are the neighbours that precede a cell in an
+ *           x-slowest, z-fastest sweep, Sec. 3).  Weights 1/3, 1/18, 1/36.
+ * Model     BGK with relaxation time tau (> 1/2); rho = sum f,
+ *           u = (sum c f + F/2)/rho; second-order equilibrium; Guo forcing
+ *           when a body-force field F is attached; halfway bounce-back on wall
+ *           faces, with the momentum term -6 w_q (c_q . u_w) of a moving face
+ *           (wall density 1) on every link that crosses it.
+ * Step      one collide followed by one stream (Sec. 3).  After any call the
+ *           distribution buffer holds the post-stream state of the last step,
+ *           in natural layout: slot q of cell x holds f_q(x).
+ * Layout    f[q][x][y][z], z fastest: element q*N + (x*ny + y)*nz + z with
+ *           N = nx*ny*nz; the stored value is the offset g = f - w_q, in the
+ *           storage type of the configuration.  Vector fields (u, F, their
+ *           gradients) are SoA: a[c*N + cell], c = 0 (x), 1 (y), 2 (z).
+ * Memory    every pointer named *_dev is device memory owned by the caller
+ *           (e.g. a torch tensor) and must stay valid while a context uses
+ *           it.  The library never allocates device memory: its scratch
+ *           (side planes, progress flags, reduction partials, the second
+ *           lattice of the two-array scheme) lives in the caller's work
+ *           buffer, sized by lbm_buffer_sizes.  Device pointers must be
+ *           256-byte aligned.
+ * Streams   every call is enqueued asynchronously on the context's stream
+ *           (a hipStream_t passed as void*; NULL is the legacy default
+ *           stream), except lbm_macroscopic with sums_host != NULL, which
+ *           waits for its result.  A context is not thread-safe; calls on
+ *           contexts that share a work buffer must not overlap.
+ * Errors    every entry point returns an lbm_status and never aborts.
+ *           Arguments are validated before any device work; on failure the
+ *           context keeps a message for lbm_last_error.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,       /* bad argument: tau <= 1/2, dims < 1, null pointer, bad face codes */
+    LBM_EUNSUPPORTED = -2, /* valid but not built: e.g. adjoint with 16-bit storage */
+    LBM_EDEVICE = -3,      /* a HIP call or kernel launch failed; message kept */
+    LBM_ESTATE = -4        /* call on a NULL or failed context */
+} lbm_status;
+
+typedef enum {
+    LBM_F64 = 0,     /* double storage and double arithmetic */
+    LBM_F32 = 1,     /* float storage and float arithmetic */
+    LBM_F16_OFS = 2, /* IEEE binary16 storage of f - w (round to nearest even), float arithmetic */
+    LBM_BF16_OFS = 3 /* bfloat16 storage of f - w (round to nearest even), float arithmetic */
+} lbm_storage;
+
+typedef enum {
+    LBM_TWO_ARRAY = 0, /* plain baseline: collide + push-stream into a second lattice (work buffer) */
+    LBM_SWAP1 = 1,     /* in place, single copy, one step per pass (Sec. 3, Alg. 1) */
+    LBM_SWAP2 = 2      /* in place, single copy, two steps merged per pass (Sec. 4.1, Alg. 2) */
+} lbm_scheme;
+
+typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_MOVING_WALL = 2 } lbm_face;
+
+typedef struct {
+    int32_t nx, ny, nz; /* lattice size, x slowest, z fastest; each >= 1 */
+    double tau;         /* BGK relaxation time, > 0.5 */
+    int32_t storage;    /* lbm_storage */
+    int32_t scheme;     /* lbm_scheme */
+    int32_t face[6];    /* -x,+x,-y,+y,-z,+z: lbm_face; both faces of an axis periodic or neither;
+                           at most one LBM_MOVING_WALL */
+    double wall_u[3];   /* velocity of the moving-wall face (ignored without one) */
+    int32_t use_force;  /* 1: a body-force density field F (3N, double for LBM_F64, float otherwise) */
+    int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes */
+} lbm_config;
+
+/* Bytes the caller must provide for the distribution buffer (19*N values of
+ * the storage type) and for the work buffer of this configuration.  Either
+ * output may be NULL. */
+lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work_bytes);
+
+/* Create a context and set f to the equilibrium of (rho0, u0) (Sec. 5.1: one
+ * cavity is built once and every algorithm runs on it).  rho0_dev: N doubles
+ * or NULL (rho = 1); u0_dev: 3N doubles (SoA) or NULL (u = 0).  force_dev is
+ * required iff cfg->use_force.  On success *out owns a new context (release
+ * with lbm_destroy); on failure *out is set to NULL. */
+lbm_status lbm_init(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev,
+                    const double* rho0_dev, const double* u0_dev, void* hip_stream, lbm_ctx** out);
+
+/* Create a context that adopts the state already in f_dev (resume from a
+ * checkpoint: the distribution buffer is the whole state). */
+lbm_status lbm_attach(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev,
+                      void* hip_stream, lbm_ctx** out);
+
+/* Advance n >= 0 time steps (Sec. 3: N steps; Sec. 5.1: N/2 merged passes).
+ * LBM_SWAP2 runs n/2 merged passes and, if n is odd, one single-step pass;
+ * LBM_TWO_ARRAY copies the state back into f_dev after an odd number of steps. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Per-cell density, velocity u = (sum c f + F/2)/rho and velocity norm |u|
+ * (the quantity compared across algorithms in Sec. 5.1), all as doubles
+ * computed in double from the stored state.  rho_dev: N, u_dev: 3N (SoA),
+ * unorm_dev: N; each may be NULL.  If sums_host is not NULL it receives
+ * { sum rho, sum_q c_x f, sum_q c_y f, sum_q c_z f } over all cells (the
+ * populations' mass and momentum, accumulated in double on the device in a
+ * fixed order), and the call waits for them. */
+lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double* unorm_dev, double* sums_host);
+
+/* Discrete adjoint, seed: given dL/du of the velocity field of the state
+ * f_dev (grad_u_dev: 3N of the arithmetic type), write lambda = dL/df
+ * (lambda_dev: 19N of the arithmetic type, not offset) and add the direct
+ * dL/dF = dL/du / (2 rho) to grad_force_dev (3N; may be NULL without a force).
+ * Supported for LBM_F64 and LBM_F32 storage. */
+lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u_dev, void* lambda_dev,
+                             void* grad_force_dev);
+
+/* Discrete adjoint of k in {1, 2} forward steps taken from the state f_t_dev
+ * (storage type and layout of f, left unchanged): lambda_in_dev holds
+ * dL/df_{t+k}; lambda_out_dev receives dL/df_t (distinct buffers, 19N of the
+ * arithmetic type); grad_force_dev (3N) accumulates the force gradient of the
+ * k steps.  With k = 2 the state f_{t+1} is recomputed on chip, so one call
+ * reads f_t once (the adjoint of the two-step merged pass). */
+lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambda_in_dev, void* lambda_out_dev,
+                            void* grad_force_dev, int32_t k);
+
+/* Measurement hook.  While enabled, every launch of the lattice-update kernel
+ * itself (the marching kernel of LBM_SWAP1/LBM_SWAP2 without its prepass, or
+ * the two-array kernel) is bracketed by a pair of HIP events recorded on the
+ * context's stream.  lbm_kernel_time waits for the recorded launches and
+ * returns their summed duration in milliseconds and their count, split by the
+ * number of steps each launch merged (index 0: one step, index 1: two steps;
+ * total_ms and launches point to arrays of 2), then forgets them.  Events are
+ * host-side objects owned by the context; no device memory is allocated. */
+lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Rebind the context to another stream (a hipStream_t as void*). */
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
+
+/* Message of the last failed call on ctx (or of the last failed lbm_init /
+ * lbm_attach when ctx is NULL); "" if none.  Valid until the next call. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Release a context; NULL is allowed.  Device buffers stay the caller's. */
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

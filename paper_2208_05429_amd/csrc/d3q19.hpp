@@ -1,0 +1,243 @@
+// d3q19.hpp -- device-side D3Q19 lattice, storage codecs and per-cell BGK
+// collision for gfx950.  The numbering follows the public header: c_0 = 0,
+// directions 1..9 point to the neighbours that precede a cell in an
+// x-slowest, z-fastest sweep (Sec. 3 of the paper, Fig. 1a), c_{q+9} = -c_q.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace lbm {
+
+constexpr int Q = 19;
+
+// ---- velocity set, evaluated at compile time inside unrolled loops ----
+__host__ __device__ constexpr int cxq(int q)
+{
+    constexpr int t[Q] = {0, -1, 0, 0, -1, -1, -1, -1, 0, 0, 1, 0, 0, 1, 1, 1, 1, 0, 0};
+    return t[q];
+}
+__host__ __device__ constexpr int cyq(int q)
+{
+    constexpr int t[Q] = {0, 0, -1, 0, -1, 1, 0, 0, -1, -1, 0, 1, 0, 1, -1, 0, 0, 1, 1};
+    return t[q];
+}
+__host__ __device__ constexpr int czq(int q)
+{
+    constexpr int t[Q] = {0, 0, 0, -1, 0, 0, -1, 1, -1, 1, 0, 0, 1, 0, 0, 1, -1, 1, -1};
+    return t[q];
+}
+__host__ __device__ constexpr int oppq(int q) { return q == 0 ? 0 : (q <= 9 ? q + 9 : q - 9); }
+__host__ __device__ constexpr int c2q(int q) { return cxq(q) * cxq(q) + cyq(q) * cyq(q) + czq(q) * czq(q); }
+template <class R>
+__host__ __device__ constexpr R wq(int q)
+{
+    return c2q(q) == 0 ? R(1) / R(3) : (c2q(q) == 1 ? R(1) / R(18) : R(1) / R(36));
+}
+// directions whose (y,z) part is nonzero move between columns of a plane
+__host__ __device__ constexpr bool moves_yz(int q) { return cyq(q) != 0 || czq(q) != 0; }
+// compact index 0..15 of the 16 column-moving directions
+__host__ __device__ constexpr int yz_index(int q)
+{
+    int k = 0;
+    for (int p = 0; p < q; ++p) k += moves_yz(p) ? 1 : 0;
+    return k;
+}
+// compact index 0..4 of the five directions with c_x = +1
+__host__ __device__ constexpr int xp_index(int q)
+{
+    int k = 0;
+    for (int p = 0; p < q; ++p) k += cxq(p) == 1 ? 1 : 0;
+    return k;
+}
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(static_cast<F&&>(f));
+    }
+}
+
+// ---- storage codecs: stored value is g = f - w_q ----
+enum : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+template <int S>
+struct Codec;
+template <>
+struct Codec<ST_F64> {
+    using T = double;
+    using R = double;
+    static __device__ __forceinline__ R dec(T v) { return v; }
+    static __device__ __forceinline__ T enc(R v) { return v; }
+};
+template <>
+struct Codec<ST_F32> {
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R dec(T v) { return v; }
+    static __device__ __forceinline__ T enc(R v) { return v; }
+};
+template <>
+struct Codec<ST_F16> {
+    using T = uint16_t;
+    using R = float;
+    static __device__ __forceinline__ R dec(T v) { return __half2float(__ushort_as_half(v)); }
+    static __device__ __forceinline__ T enc(R v) { return __half_as_ushort(__float2half_rn(v)); }
+};
+template <>
+struct Codec<ST_BF16> {
+    using T = uint16_t;
+    using R = float;
+    static __device__ __forceinline__ R dec(T v) { return __uint_as_float(uint32_t(v) << 16); }
+    static __device__ __forceinline__ T enc(R v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return T((u >> 16) | 0x40u);  // quiet NaN
+        u += 0x7fffu + ((u >> 16) & 1u);                                    // round to nearest even
+        return T(u >> 16);
+    }
+};
+
+// Momentum term of a moving wall for the population entering along c_q after
+// bouncing: 6 w_q (c_q . u_w) (halfway bounce-back, wall density 1).  Every
+// kernel uses this one expression so that the schemes agree to the last bit.
+template <int q, class R>
+__device__ __forceinline__ R wall_term(R uwx, R uwy, R uwz)
+{
+    R cu = R(0);
+    if constexpr (cxq(q) != 0) cu += R(cxq(q)) * uwx;
+    if constexpr (cyq(q) != 0) cu += R(cyq(q)) * uwy;
+    if constexpr (czq(q) != 0) cu += R(czq(q)) * uwz;
+    constexpr R w6 = R(6) * wq<R>(q);
+    return w6 * cu;
+}
+
+// ---- per-cell physics in offset form ----
+//
+// With g_q = f_q - w_q: rho = 1 + sum g, j = sum c g, u = (j + F/2)/rho and
+// geq_q = feq_q - w_q = w_q [ (rho - 1) + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u) ].
+// BGK: g*_q = g_q - omega (g_q - geq_q) + S_q, Guo forcing
+// S_q = (1 - omega/2) w_q [3 (c_q - u) + 9 (c_q.u) c_q] . F.
+// Each direction q in 1..9 is handled together with its opposite q+9: the
+// equilibrium and forcing split into a part even in c and a part odd in c.
+//
+// The odd part, 3 w_q c_q . (omega rho u + (1 - omega/2) F), carries the
+// momentum.  It is evaluated from j itself (rho u = j + F/2 exactly) with
+// coefficients K1 = 3 w (|c| = 1) and K2 = 3 w (|c|^2 = 2) rounded so that
+// 2 K1 + 8 K2 = 1 holds exactly in the arithmetic type: the collision then
+// hands back exactly the momentum it received.  With K1 = fl(1/6) instead,
+// every FP32 collision scales the momentum by (1 + omega * 3e-8), a bias that
+// grows linearly in time (4e-6 of the velocity after 100 steps at tau = 0.8).
+
+template <class R>
+struct Moments {
+    R drho, rho, jx, jy, jz;  // j includes F/2
+    R ux, uy, uz;
+};
+
+template <class R, bool FORCE>
+__device__ __forceinline__ Moments<R> moments(const R (&g)[Q], R Fx, R Fy, R Fz)
+{
+    R s[10], d[10];
+    sfor<1, 10>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        s[q] = g[q] + g[q + 9];
+        d[q] = g[q] - g[q + 9];
+    });
+    Moments<R> m;
+    m.drho = g[0] + (((s[1] + s[2]) + (s[3] + s[4])) + ((s[5] + s[6]) + (s[7] + (s[8] + s[9]))));
+    // j = sum_{q=1..9} c_q (g_q - g_{q+9}); every c_q here has components in {-1, 0, 1}
+    m.jx = -((d[1] + d[4]) + (d[5] + (d[6] + d[7])));
+    m.jy = -((d[2] + d[4]) + ((d[8] + d[9]) - d[5]));
+    m.jz = -((d[3] + d[6]) + ((d[8] - d[9]) - d[7]));
+    if constexpr (FORCE) {
+        m.jx = fma(R(0.5), Fx, m.jx);
+        m.jy = fma(R(0.5), Fy, m.jy);
+        m.jz = fma(R(0.5), Fz, m.jz);
+    }
+    m.rho = R(1) + m.drho;
+    const R inv = R(1) / m.rho;
+    m.ux = m.jx * inv;
+    m.uy = m.jy * inv;
+    m.uz = m.jz * inv;
+    return m;
+}
+
+// 3 w_q, rounded so that the odd parts return exactly the momentum they get
+template <class R>
+__device__ __forceinline__ constexpr R k_diag()
+{
+    return R(1) / R(12);
+}
+template <class R>
+__device__ __forceinline__ constexpr R k_axis()
+{
+    return (R(1) - R(8) * k_diag<R>()) / R(2);
+}
+
+// Every multiply-add is an explicit fma() and the library is compiled without
+// floating-point contraction, so this arithmetic is the same instruction
+// sequence in every kernel: the three schemes agree to the last bit.
+template <class R, bool FORCE>
+__device__ __forceinline__ void collide(R (&g)[Q], R omega, R Fx = R(0), R Fy = R(0), R Fz = R(0))
+{
+    const Moments<R> m = moments<R, FORCE>(g, Fx, Fy, Fz);
+    const R omw = R(1) - omega;
+    const R usq15 = R(1.5) * fma(m.ux, m.ux, fma(m.uy, m.uy, m.uz * m.uz));
+    const R od = omega * m.drho, orho = omega * m.rho;
+    // odd-part momentum: omega (j + F/2) + (1 - omega/2) F
+    R ax = omega * m.jx, ay = omega * m.jy, az = omega * m.jz;
+    R kF = R(0), uF = R(0);
+    if constexpr (FORCE) {
+        kF = fma(R(-0.5), omega, R(1));
+        uF = fma(m.ux, Fx, fma(m.uy, Fy, m.uz * Fz));
+        ax = fma(kF, Fx, ax);
+        ay = fma(kF, Fy, ay);
+        az = fma(kF, Fz, az);
+    }
+    {
+        constexpr R w0 = wq<R>(0);
+        R e0 = w0 * fma(-orho, usq15, od);
+        if constexpr (FORCE) e0 = fma(R(-3) * w0 * kF, uF, e0);
+        g[0] = fma(omw, g[0], e0);
+    }
+    sfor<1, 10>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr R w = wq<R>(q);
+        constexpr int cx = cxq(q), cy = cyq(q), cz = czq(q);
+        const R K = c2q(q) == 1 ? k_axis<R>() : k_diag<R>();
+        R cu = R(0), ca = R(0);
+        if constexpr (cx != 0) {
+            cu += R(cx) * m.ux;
+            ca += R(cx) * ax;
+        }
+        if constexpr (cy != 0) {
+            cu += R(cy) * m.uy;
+            ca += R(cy) * ay;
+        }
+        if constexpr (cz != 0) {
+            cu += R(cz) * m.uz;
+            ca += R(cz) * az;
+        }
+        // even part w [omega drho + omega rho (9/2 cu^2 - 3/2 u^2)]
+        R even = w * fma(orho, fma(R(4.5) * cu, cu, -usq15), od);
+        if constexpr (FORCE) {
+            R cF = R(0);
+            if constexpr (cx != 0) cF += R(cx) * Fx;
+            if constexpr (cy != 0) cF += R(cy) * Fy;
+            if constexpr (cz != 0) cF += R(cz) * Fz;
+            even = fma(kF * w, fma(R(9) * cu, cF, R(-3) * uF), even);
+        }
+        const R odd = K * ca;
+        g[q] = fma(omw, g[q], even + odd);
+        g[q + 9] = fma(omw, g[q + 9], even - odd);
+    });
+}
+
+}  // namespace lbm

@@ -1,0 +1,242 @@
+// k_adjoint.hip -- discrete adjoint of the D3Q19 BGK step (stream^T and
+// collide^T per cell), for gradients of a loss of the final velocity field
+// with respect to a per-cell body force.
+//
+// One forward step is f_{t+1} = S(C(f_t; F)) with S the push streaming with
+// bounce-back (a permutation plus a constant wall term) and C the per-cell
+// collision.  Its adjoint maps lambda_{t+1} = dL/df_{t+1} to
+//   mu = S^T lambda_{t+1}:  mu_q(x) = lambda_q(x + c_q), or lambda_opp(q)(x)
+//        when the link leaves through a wall;
+//   lambda_t = (dC/df)^T mu and dL/dF += (dC/dF)^T mu, per cell.
+// With A = sum_q mu_q w_q, B = sum_q mu_q w_q c_q, C = sum_q mu_q w_q c_q c_q
+// (omega = 1/tau, k = 1 - omega/2):
+//   g_rho = omega [A (1 - 3/2 u.u) + 3 B.u + 9/2 u.C.u]
+//   g_u   = omega rho [3 B + 9 C u - 3 A u] + k [9 C F - 3 A F]
+//   lambda_j = (1 - omega) mu_j + g_rho + g_u . (c_j - u) / rho
+//   dL/dF += k [3 B - 3 A u + 9 C u] + g_u / (2 rho)
+#include "d3q19.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+template <class R, bool FORCE>
+__device__ __forceinline__ void collide_adjoint(const R (&g)[Q], const R (&mu)[Q], R omega, R Fx, R Fy, R Fz,
+                                                R (&lam)[Q], R& gFx, R& gFy, R& gFz)
+{
+    const Moments<R> m = moments<R, FORCE>(g, Fx, Fy, Fz);
+    R A = R(0), Bx = R(0), By = R(0), Bz = R(0);
+    R Cxx = R(0), Cyy = R(0), Czz = R(0), Cxy = R(0), Cxz = R(0), Cyz = R(0);
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const R mw = mu[q] * wq<R>(q);
+        A += mw;
+        if constexpr (cxq(q) != 0) Bx += R(cxq(q)) * mw;
+        if constexpr (cyq(q) != 0) By += R(cyq(q)) * mw;
+        if constexpr (czq(q) != 0) Bz += R(czq(q)) * mw;
+        if constexpr (cxq(q) != 0) Cxx += mw;
+        if constexpr (cyq(q) != 0) Cyy += mw;
+        if constexpr (czq(q) != 0) Czz += mw;
+        if constexpr (cxq(q) * cyq(q) != 0) Cxy += R(cxq(q) * cyq(q)) * mw;
+        if constexpr (cxq(q) * czq(q) != 0) Cxz += R(cxq(q) * czq(q)) * mw;
+        if constexpr (cyq(q) * czq(q) != 0) Cyz += R(cyq(q) * czq(q)) * mw;
+    });
+    const R ux = m.ux, uy = m.uy, uz = m.uz, rho = m.rho;
+    const R Cux = Cxx * ux + Cxy * uy + Cxz * uz;
+    const R Cuy = Cxy * ux + Cyy * uy + Cyz * uz;
+    const R Cuz = Cxz * ux + Cyz * uy + Czz * uz;
+    const R usq = ux * ux + uy * uy + uz * uz;
+    const R g_rho = omega * (A * (R(1) - R(1.5) * usq) + R(3) * (Bx * ux + By * uy + Bz * uz) +
+                             R(4.5) * (ux * Cux + uy * Cuy + uz * Cuz));
+    const R orho = omega * rho;
+    R gux = orho * (R(3) * Bx + R(9) * Cux - R(3) * A * ux);
+    R guy = orho * (R(3) * By + R(9) * Cuy - R(3) * A * uy);
+    R guz = orho * (R(3) * Bz + R(9) * Cuz - R(3) * A * uz);
+    const R kF = R(1) - R(0.5) * omega;
+    if constexpr (FORCE) {
+        gux += kF * (R(9) * (Cxx * Fx + Cxy * Fy + Cxz * Fz) - R(3) * A * Fx);
+        guy += kF * (R(9) * (Cxy * Fx + Cyy * Fy + Cyz * Fz) - R(3) * A * Fy);
+        guz += kF * (R(9) * (Cxz * Fx + Cyz * Fy + Czz * Fz) - R(3) * A * Fz);
+    }
+    const R inv = R(1) / rho;
+    const R gdu = (gux * ux + guy * uy + guz * uz) * inv;
+    const R omw = R(1) - omega;
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        R cg = R(0);
+        if constexpr (cxq(q) != 0) cg += R(cxq(q)) * gux;
+        if constexpr (cyq(q) != 0) cg += R(cyq(q)) * guy;
+        if constexpr (czq(q) != 0) cg += R(czq(q)) * guz;
+        lam[q] = omw * mu[q] + g_rho + (cg * inv - gdu);
+    });
+    const R i2 = R(0.5) * inv;
+    gFx = kF * (R(3) * Bx - R(3) * A * ux + R(9) * Cux) + gux * i2;
+    gFy = kF * (R(3) * By - R(3) * A * uy + R(9) * Cuy) + guy * i2;
+    gFz = kF * (R(3) * Bz - R(3) * A * uz + R(9) * Cuz) + guz * i2;
+}
+
+// lambda := dL/df from dL/du of the state f; gradF += dL/du / (2 rho)
+template <int S, bool FORCE>
+__global__ __launch_bounds__(256) void k_macro_adjoint(Geom g, const typename Codec<S>::T* __restrict__ f,
+                                                       const typename Codec<S>::R* __restrict__ F,
+                                                       const typename Codec<S>::R* __restrict__ gu,
+                                                       typename Codec<S>::R* __restrict__ lam,
+                                                       typename Codec<S>::R* __restrict__ gF)
+{
+    using Cd = Codec<S>;
+    using R = typename Cd::R;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.N) return;
+    R v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(f[q * g.N + i]);
+    R Fx = R(0), Fy = R(0), Fz = R(0);
+    if constexpr (FORCE) {
+        Fx = F[i];
+        Fy = F[g.N + i];
+        Fz = F[2 * g.N + i];
+    }
+    const Moments<R> m = moments<R, FORCE>(v, Fx, Fy, Fz);
+    const R inv = R(1) / m.rho;
+    const R gx = gu[i], gy = gu[g.N + i], gz = gu[2 * g.N + i];
+    const R gdu = gx * m.ux + gy * m.uy + gz * m.uz;
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        R cg = R(0);
+        if constexpr (cxq(q) != 0) cg += R(cxq(q)) * gx;
+        if constexpr (cyq(q) != 0) cg += R(cyq(q)) * gy;
+        if constexpr (czq(q) != 0) cg += R(czq(q)) * gz;
+        lam[q * g.N + i] = (cg - gdu) * inv;
+    });
+    if (gF) {
+        const R h = R(0.5) * inv;
+        gF[i] += gx * h;
+        gF[g.N + i] += gy * h;
+        gF[2 * g.N + i] += gz * h;
+    }
+}
+
+// mu_q(x): lambda_q at the target of the link (x, q), or lambda_opp(q)(x) when
+// the link leaves through a wall face
+template <class R, bool WALLS>
+__device__ __forceinline__ void stream_adjoint_gather(const Geom& g, const R* __restrict__ lin, int x, int y, int z,
+                                                      long long i, R (&mu)[Q])
+{
+    const int n[3] = {g.nx, g.ny, g.nz};
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int c[3] = {cxq(q), cyq(q), czq(q)};
+        int p[3] = {x + c[0], y + c[1], z + c[2]};
+        bool out = false;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (c[ax] == 0 || (p[ax] >= 0 && p[ax] < n[ax])) continue;
+            if (WALLS && g.wall[ax])
+                out = true;
+            else
+                p[ax] = p[ax] < 0 ? p[ax] + n[ax] : p[ax] - n[ax];
+        }
+        if (WALLS && out)
+            mu[q] = lin[oppq(q) * g.N + i];
+        else
+            mu[q] = lin[q * g.N + ((long long)p[0] * g.ny + p[1]) * g.nz + p[2]];
+    });
+}
+
+// one reverse step: lam_out = adjoint of one step at f_t applied to lam_in
+template <int S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_adjoint1(Geom g, const typename Codec<S>::T* __restrict__ ft,
+                                                  const typename Codec<S>::R* __restrict__ F,
+                                                  const typename Codec<S>::R* __restrict__ lin,
+                                                  typename Codec<S>::R* __restrict__ lout,
+                                                  typename Codec<S>::R* __restrict__ gF)
+{
+    using Cd = Codec<S>;
+    using R = typename Cd::R;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.N) return;
+    const int z = int(i % g.nz);
+    const long long r = i / g.nz;
+    const int y = int(r % g.ny), x = int(r / g.ny);
+    R mu[Q], v[Q], lam[Q];
+    stream_adjoint_gather<R, WALLS>(g, lin, x, y, z, i, mu);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(ft[q * g.N + i]);
+    R Fx = R(0), Fy = R(0), Fz = R(0);
+    if constexpr (FORCE) {
+        Fx = F[i];
+        Fy = F[g.N + i];
+        Fz = F[2 * g.N + i];
+    }
+    R gx, gy, gz;
+    collide_adjoint<R, FORCE>(v, mu, R(g.omega), Fx, Fy, Fz, lam, gx, gy, gz);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lout[q * g.N + i] = lam[q];
+    if (FORCE && gF) {
+        gF[i] += gx;
+        gF[g.N + i] += gy;
+        gF[2 * g.N + i] += gz;
+    }
+}
+
+template <int S, bool FORCE>
+static hipError_t macro_adjoint_s(const Geom& g, const void* f, const void* F, const void* gu, void* lam, void* gF,
+                                  hipStream_t s)
+{
+    using Cd = Codec<S>;
+    using R = typename Cd::R;
+    hipLaunchKernelGGL((k_macro_adjoint<S, FORCE>), dim3(unsigned((g.N + 255) / 256)), dim3(256), 0, s, g,
+                       static_cast<const typename Cd::T*>(f), static_cast<const R*>(F), static_cast<const R*>(gu),
+                       static_cast<R*>(lam), static_cast<R*>(gF));
+    return hipGetLastError();
+}
+
+hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const void* f, const void* F,
+                                const void* grad_u, void* lambda, void* grad_force, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64:
+        return force ? macro_adjoint_s<ST_F64, true>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_F64, false>(g, f, F, grad_u, lambda, grad_force, s);
+    case ST_F32:
+        return force ? macro_adjoint_s<ST_F32, true>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_F32, false>(g, f, F, grad_u, lambda, grad_force, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int S, bool FORCE>
+static hipError_t adjoint1_s(const Geom& g, const void* ft, const void* F, const void* lin, void* lout, void* gF,
+                             hipStream_t s)
+{
+    using Cd = Codec<S>;
+    using R = typename Cd::R;
+    const bool walls = g.wall[0] || g.wall[1] || g.wall[2];
+    auto fp = static_cast<const typename Cd::T*>(ft);
+    auto Fp = static_cast<const R*>(F);
+    auto li = static_cast<const R*>(lin);
+    auto lo = static_cast<R*>(lout);
+    auto gp = static_cast<R*>(gF);
+    const dim3 grid(unsigned((g.N + 255) / 256));
+    if (walls)
+        hipLaunchKernelGGL((k_adjoint1<S, true, FORCE>), grid, dim3(256), 0, s, g, fp, Fp, li, lo, gp);
+    else
+        hipLaunchKernelGGL((k_adjoint1<S, false, FORCE>), grid, dim3(256), 0, s, g, fp, Fp, li, lo, gp);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, const void* f_t, const void* F,
+                               const void* lam_in, void* lam_out, void* grad_force, hipStream_t s)
+{
+    if (k != 1) return hipErrorNotSupported;
+    switch (storage) {
+    case ST_F64:
+        return force ? adjoint1_s<ST_F64, true>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_F64, false>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F32:
+        return force ? adjoint1_s<ST_F32, true>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_F32, false>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -1,0 +1,295 @@
+// k_basic.hip -- equilibrium initialisation, the plain two-array baseline step,
+// the marching-pass prepass, macroscopic fields with FP64 conservation sums,
+// and the storage-type dispatch of every launcher.
+#include "d3q19.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// ------------------------------------------------------------------------
+// f := f_eq(rho0, u0), stored as g = f - w (Sec. 5.1: every algorithm starts
+// from the same constructed state).  Evaluated in double, rounded once.
+// ------------------------------------------------------------------------
+template <int S>
+__global__ __launch_bounds__(256) void k_init(Geom g, typename Codec<S>::T* f, const double* rho0, const double* u0)
+{
+    using Cd = Codec<S>;
+    using R = typename Cd::R;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.N) return;
+    const double rho = rho0 ? rho0[i] : 1.0;
+    const double ux = u0 ? u0[i] : 0.0, uy = u0 ? u0[g.N + i] : 0.0, uz = u0 ? u0[2 * g.N + i] : 0.0;
+    const double usq = ux * ux + uy * uy + uz * uz;
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double cu = cxq(q) * ux + cyq(q) * uy + czq(q) * uz;
+        const double geq = wq<double>(q) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+        f[q * g.N + i] = Cd::enc(R(geq));
+    });
+}
+
+// ------------------------------------------------------------------------
+// Plain baseline: one collide + push-stream step from src into dst (a second
+// lattice), one thread per cell.  Same per-cell arithmetic as the in-place
+// kernels, so the three schemes agree to the last bit.
+// ------------------------------------------------------------------------
+template <int S, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(256) void k_two_array(Geom g, const typename Codec<S>::T* __restrict__ src,
+                                                   typename Codec<S>::T* __restrict__ dst,
+                                                   const typename Codec<S>::R* __restrict__ F)
+{
+    using Cd = Codec<S>;
+    using R = typename Cd::R;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= g.N) return;
+    const int z = int(i % g.nz);
+    const long long r = i / g.nz;
+    const int y = int(r % g.ny), x = int(r / g.ny);
+    R v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(src[q * g.N + i]);
+    R Fx = R(0), Fy = R(0), Fz = R(0);
+    if constexpr (FORCE) {
+        Fx = F[i];
+        Fy = F[g.N + i];
+        Fz = F[2 * g.N + i];
+    }
+    collide<R, FORCE>(v, R(g.omega), Fx, Fy, Fz);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const int c[3] = {cxq(q), cyq(q), czq(q)};
+        int p[3] = {x + c[0], y + c[1], z + c[2]};
+        bool out = false, moving = false;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (c[ax] == 0 || (p[ax] >= 0 && p[ax] < n[ax])) continue;
+            const int face = 2 * ax + (p[ax] >= n[ax] ? 1 : 0);
+            if (WALLS && g.wall[ax]) {
+                out = true;
+                if (face == g.moving_face) moving = true;
+            } else {
+                p[ax] = p[ax] < 0 ? p[ax] + n[ax] : p[ax] - n[ax];
+            }
+        }
+        if (WALLS && out) {
+            R val = v[q];
+            if (moving) val += wall_term<oppq(q)>(R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+            dst[oppq(q) * g.N + i] = Cd::enc(val);
+        } else {
+            dst[q * g.N + ((long long)p[0] * g.ny + p[1]) * g.nz + p[2]] = Cd::enc(v[q]);
+        }
+    });
+}
+
+// ------------------------------------------------------------------------
+// Prepass of a marching pass: save the time-t copies of the first M planes of
+// every segment and clear the progress counters (flags[0] is the timeout
+// word, flags[1..] one counter per work item).
+// ------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_prepass(Geom g, const T* __restrict__ f, T* __restrict__ side, int* flags,
+                                                 int nflags, int M, int seg_len, int nseg)
+{
+    const long long per = (long long)Q * g.PL;
+    const long long total = (long long)nseg * M * per;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        const long long bj = t / per, rem = t - bj * per;
+        const long long q = rem / g.PL, o = rem - q * g.PL;
+        const int b = int(bj / M), j = int(bj - (long long)b * M);
+        const int plane = (b * seg_len + j) % g.nx;
+        side[t] = f[q * g.N + (long long)plane * g.PL + o];
+    }
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < nflags; t += (long long)gridDim.x * 256)
+        flags[t] = 0;
+}
+
+// ------------------------------------------------------------------------
+// Macroscopic fields in double from the stored state, and per-block FP64
+// partial sums of (sum g, j) reduced with wavefront shuffles.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    return t;
+}
+
+template <int S, bool FORCE>
+__global__ __launch_bounds__(256) void k_macro(Geom g, const typename Codec<S>::T* __restrict__ f,
+                                               const typename Codec<S>::R* __restrict__ F, double* rho_out,
+                                               double* u_out, double* un_out, double* partials)
+{
+    using Cd = Codec<S>;
+    __shared__ double sh[4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < g.N; i += (long long)gridDim.x * 256) {
+        double gq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) gq[q] = double(Cd::dec(f[q * g.N + i]));
+        double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        sfor<0, Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            drho += gq[q];
+            if constexpr (cxq(q) != 0) jx += cxq(q) * gq[q];
+            if constexpr (cyq(q) != 0) jy += cyq(q) * gq[q];
+            if constexpr (czq(q) != 0) jz += czq(q) * gq[q];
+        });
+        acc[0] += drho;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += jz;
+        const double rho = 1.0 + drho;
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+        if constexpr (FORCE) {
+            Fx = double(F[i]);
+            Fy = double(F[g.N + i]);
+            Fz = double(F[2 * g.N + i]);
+        }
+        const double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
+        if (rho_out) rho_out[i] = rho;
+        if (u_out) {
+            u_out[i] = ux;
+            u_out[g.N + i] = uy;
+            u_out[2 * g.N + i] = uz;
+        }
+        if (un_out) un_out[i] = sqrt(ux * ux + uy * uy + uz * uz);
+    }
+    if (partials) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double t = block_sum(acc[k], sh);
+            if (threadIdx.x == 0) partials[blockIdx.x * 4 + k] = t;
+        }
+    }
+}
+
+// sums = { N + sum g, sum j } from the per-block partials, in a fixed order
+__global__ __launch_bounds__(256) void k_sums(const double* partials, int nblocks, double ncell, double* sums)
+{
+    __shared__ double sh[4];
+    for (int k = 0; k < 4; ++k) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) v += partials[b * 4 + k];
+        const double t = block_sum(v, sh);
+        if (threadIdx.x == 0) sums[k] = (k == 0 ? ncell : 0.0) + t;
+    }
+}
+
+// ------------------------------------------------------------------------
+// dispatch
+// ------------------------------------------------------------------------
+static unsigned grid_for(long long n) { return unsigned((n + 255) / 256); }
+
+template <int S>
+static hipError_t init_s(const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init<S>, dim3(grid_for(g.N)), dim3(256), 0, s, g, static_cast<typename Codec<S>::T*>(f),
+                       rho0, u0);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return init_s<ST_F64>(g, f, rho0, u0, s);
+    case ST_F32: return init_s<ST_F32>(g, f, rho0, u0, s);
+    case ST_F16: return init_s<ST_F16>(g, f, rho0, u0, s);
+    case ST_BF16: return init_s<ST_BF16>(g, f, rho0, u0, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int S, bool FORCE>
+static hipError_t two_array_s(const Geom& g, const void* src, void* dst, const void* F, hipStream_t s)
+{
+    using Cd = Codec<S>;
+    const bool walls = g.wall[0] || g.wall[1] || g.wall[2];
+    auto sp = static_cast<const typename Cd::T*>(src);
+    auto dp = static_cast<typename Cd::T*>(dst);
+    auto fp = static_cast<const typename Cd::R*>(F);
+    if (walls)
+        hipLaunchKernelGGL((k_two_array<S, true, FORCE>), dim3(grid_for(g.N)), dim3(256), 0, s, g, sp, dp, fp);
+    else
+        hipLaunchKernelGGL((k_two_array<S, false, FORCE>), dim3(grid_for(g.N)), dim3(256), 0, s, g, sp, dp, fp);
+    return hipGetLastError();
+}
+
+hipError_t launch_two_array(int storage, bool force, const Geom& g, const void* src, void* dst, const void* F,
+                            hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return force ? two_array_s<ST_F64, true>(g, src, dst, F, s) : two_array_s<ST_F64, false>(g, src, dst, F, s);
+    case ST_F32: return force ? two_array_s<ST_F32, true>(g, src, dst, F, s) : two_array_s<ST_F32, false>(g, src, dst, F, s);
+    case ST_F16: return force ? hipErrorInvalidValue : two_array_s<ST_F16, false>(g, src, dst, F, s);
+    case ST_BF16: return force ? hipErrorInvalidValue : two_array_s<ST_BF16, false>(g, src, dst, F, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(int storage, const Geom& g, const void* src, void* dst, hipStream_t s)
+{
+    const size_t elem = storage == ST_F64 ? 8 : (storage == ST_F32 ? 4 : 2);
+    return hipMemcpyAsync(dst, src, size_t(Q) * size_t(g.N) * elem, hipMemcpyDeviceToDevice, s);
+}
+
+template <class T>
+static hipError_t prepass_t(const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags, hipStream_t s)
+{
+    const long long total = (long long)p.nseg * p.M * Q * g.PL;
+    long long blocks = (total + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_prepass<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
+                       static_cast<T*>(side), flags, p.blocks + 1, p.M, p.seg_len, p.nseg);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepass(int storage, const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags,
+                          hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return prepass_t<double>(g, p, f, side, flags, s);
+    case ST_F32: return prepass_t<float>(g, p, f, side, flags, s);
+    default: return prepass_t<uint16_t>(g, p, f, side, flags, s);
+    }
+}
+
+template <int S, bool FORCE>
+static hipError_t macro_s(const Geom& g, const void* f, const void* F, double* rho, double* u, double* un,
+                          double* partials, double* sums, hipStream_t s)
+{
+    using Cd = Codec<S>;
+    hipLaunchKernelGGL((k_macro<S, FORCE>), dim3(SUM_BLOCKS), dim3(256), 0, s, g,
+                       static_cast<const typename Cd::T*>(f), static_cast<const typename Cd::R*>(F), rho, u, un,
+                       sums ? partials : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !sums) return e;
+    hipLaunchKernelGGL(k_sums, dim3(1), dim3(256), 0, s, partials, SUM_BLOCKS, double(g.N), sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(int storage, bool force, const Geom& g, const void* f, const void* F, double* rho, double* u,
+                        double* unorm, double* partials, double* sums, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64:
+        return force ? macro_s<ST_F64, true>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_F64, false>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_F32:
+        return force ? macro_s<ST_F32, true>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_F32, false>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_F16: return macro_s<ST_F16, false>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_BF16: return macro_s<ST_BF16, false>(g, f, F, rho, u, unorm, partials, sums, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

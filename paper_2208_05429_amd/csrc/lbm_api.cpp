@@ -1,0 +1,510 @@
+// lbm_api.cpp -- the C ABI declared in include/lbm.h: argument validation,
+// work-buffer layout, pass planning and kernel dispatch.  All device memory
+// belongs to the caller; this file never allocates any.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.hpp"
+#include "march_dispatch.hpp"
+
+using namespace lbm;
+
+struct lbm_ctx {
+    lbm_config cfg;
+    Geom g;
+    void* f = nullptr;
+    unsigned char* work = nullptr;
+    const void* force = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+    MarchPlan plan[3];  // indexed by M
+    size_t off_partials = 0, off_sums = 0, off_second = 0, off_flags = 0, off_side = 0;
+    // measurement hook: event pairs around update-kernel launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // 2 per recorded launch, reused
+    std::vector<int> ev_steps;   // steps merged by each recorded launch
+    size_t ev_used = 0;
+    ~lbm_ctx()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+constexpr int kMaxResident = 256;  // MI355X: 256 CUs, one marching workgroup per CU
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+size_t elem_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
+size_t real_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+lbm_status fail(std::string* where, lbm_status st, const std::string& msg)
+{
+    if (where) *where = msg;
+    return st;
+}
+
+bool march_shape_of(int storage, int M, int variant, int* TY, int* TZ, int* NT)
+{
+    const ShapeEntry* tab = storage == LBM_F64 ? kShapesF64 : kShapesF32;
+    const int n = storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
+                                     : int(sizeof(kShapesF32) / sizeof(ShapeEntry));
+    const int idx = 2 * variant + (M == 2 ? 0 : 1);
+    if (variant < 0 || idx >= n || tab[idx].M != M) return false;
+    *TY = tab[idx].TY;
+    *TZ = tab[idx].TZ;
+    *NT = tab[idx].NT;
+    return true;
+}
+
+// Tiles, segments and the hazard neighbourhood of one marching pass.
+lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::string* why)
+{
+    MarchPlan r;
+    r.M = M;
+    if (!march_shape_of(c.storage, M, c.variant, &r.TY, &r.TZ, &r.NT))
+        return fail(why, LBM_EUNSUPPORTED, "no compiled marching kernel for this storage/variant");
+    r.nty = (c.ny + r.TY - 1) / r.TY;
+    r.ntz = (c.nz + r.TZ - 1) / r.TZ;
+    const int tiles = r.nty * r.ntz;
+    if (tiles > cap)
+        return fail(why, LBM_EUNSUPPORTED,
+                    "the y-z plane needs more marching workgroups (" + std::to_string(tiles) +
+                        ") than can be co-resident (" + std::to_string(cap) + ")");
+    // a periodic axis whose last tile is thinner than M lets halos reach two tiles away
+    const bool py = c.face[2] == LBM_PERIODIC, pz = c.face[4] == LBM_PERIODIC;
+    r.ry = (py && r.nty > 1 && c.ny % r.TY != 0 && c.ny % r.TY < M) ? 2 : 1;
+    r.rz = (pz && r.ntz > 1 && c.nz % r.TZ != 0 && c.nz % r.TZ < M) ? 2 : 1;
+    // x segments: as many as fit, each at least 4M planes long
+    int nseg = cap / tiles;
+    const int by_len = c.nx / (4 * M);
+    if (nseg > by_len) nseg = by_len;
+    if (nseg < 1) nseg = 1;
+    int seg_len = (c.nx + nseg - 1) / nseg;
+    nseg = (c.nx + seg_len - 1) / seg_len;
+    while (nseg > 1 && c.nx - (nseg - 1) * seg_len < 2 * M) {
+        --nseg;
+        seg_len = (c.nx + nseg - 1) / nseg;
+        nseg = (c.nx + seg_len - 1) / seg_len;
+    }
+    r.nseg = nseg;
+    r.seg_len = seg_len;
+    r.blocks = tiles * nseg;
+    r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
+    r.side_bytes = size_t(nseg) * size_t(M) * 19u * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
+    r.flag_bytes = size_t(r.blocks + 1) * sizeof(int);
+    *p = r;
+    return LBM_OK;
+}
+
+lbm_status validate(const lbm_config* c, std::string* why)
+{
+    if (!c) return fail(why, LBM_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(why, LBM_EINVAL, "lattice dimensions must be >= 1");
+    if ((long long)c->ny * (long long)c->nz >= (1LL << 31))
+        return fail(why, LBM_EINVAL, "ny*nz must be below 2^31");
+    if (!(c->tau > 0.5) || !isfinite(c->tau)) return fail(why, LBM_EINVAL, "tau must be a finite number > 0.5");
+    if (c->storage < LBM_F64 || c->storage > LBM_BF16_OFS) return fail(why, LBM_EINVAL, "unknown storage type");
+    if (c->scheme < LBM_TWO_ARRAY || c->scheme > LBM_SWAP2) return fail(why, LBM_EINVAL, "unknown scheme");
+    if (c->use_force != 0 && c->use_force != 1) return fail(why, LBM_EINVAL, "use_force must be 0 or 1");
+    int moving = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int lo = c->face[2 * a], hi = c->face[2 * a + 1];
+        if (lo < LBM_PERIODIC || lo > LBM_MOVING_WALL || hi < LBM_PERIODIC || hi > LBM_MOVING_WALL)
+            return fail(why, LBM_EINVAL, "unknown face code");
+        if ((lo == LBM_PERIODIC) != (hi == LBM_PERIODIC))
+            return fail(why, LBM_EINVAL, "both faces of an axis must be periodic, or neither");
+        moving += (lo == LBM_MOVING_WALL) + (hi == LBM_MOVING_WALL);
+    }
+    if (moving > 1) return fail(why, LBM_EINVAL, "at most one moving-wall face");
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(c->wall_u[a])) return fail(why, LBM_EINVAL, "wall velocity must be finite");
+    if (c->use_force && c->storage != LBM_F64 && c->storage != LBM_F32)
+        return fail(why, LBM_EUNSUPPORTED, "a body force is built for FP64 and FP32 storage only");
+    if (c->variant < 0) return fail(why, LBM_EINVAL, "variant must be >= 0");
+    return LBM_OK;
+}
+
+// work buffer layout; plans use the device's co-residency cap
+lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[3], size_t off[5], size_t* total, std::string* why)
+{
+    const long long N = (long long)c.nx * c.ny * c.nz;
+    size_t o = 0;
+    off[0] = o;  // reduction partials
+    o = align_up(o + size_t(SUM_BLOCKS) * 4 * sizeof(double));
+    off[1] = o;  // final sums
+    o = align_up(o + 4 * sizeof(double));
+    off[2] = off[3] = off[4] = 0;
+    if (c.scheme == LBM_TWO_ARRAY) {
+        off[2] = o;  // the second lattice of the plain scheme
+        o = align_up(o + size_t(19) * size_t(N) * elem_size(c.storage));
+    } else {
+        size_t flags = 0, side = 0;
+        for (int M = 1; M <= 2; ++M) {
+            if (M == 2 && c.scheme != LBM_SWAP2) continue;
+            lbm_status st = make_plan(c, M, cap, &plans[M], why);
+            if (st != LBM_OK) return st;
+            if (plans[M].flag_bytes > flags) flags = plans[M].flag_bytes;
+            if (plans[M].side_bytes > side) side = plans[M].side_bytes;
+        }
+        off[3] = o;
+        o = align_up(o + flags);
+        off[4] = o;
+        o = align_up(o + side);
+    }
+    *total = o;
+    return LBM_OK;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) % kAlign) == 0; }
+
+lbm_status device_err(lbm_ctx* ctx, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LBM_OK;
+    ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EDEVICE;
+}
+
+int device_cap(const lbm_config& c, const MarchPlan& p)
+{
+    const bool walls = c.face[0] != LBM_PERIODIC || c.face[2] != LBM_PERIODIC || c.face[4] != LBM_PERIODIC;
+    const bool force = c.use_force != 0;
+    switch (c.storage) {
+    case LBM_F64: return max_blocks_f64(walls, force, p);
+    case LBM_F32: return max_blocks_f32(walls, force, p);
+    case LBM_F16_OFS: return max_blocks_f16(walls, force, p);
+    default: return max_blocks_bf16(walls, force, p);
+    }
+}
+
+lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev, void* stream,
+                  lbm_ctx** out)
+{
+    if (out) *out = nullptr;
+    g_create_err.clear();
+    if (!out) return fail(&g_create_err, LBM_EINVAL, "out is NULL");
+    lbm_status st = validate(cfg, &g_create_err);
+    if (st != LBM_OK) return st;
+    if (!f_dev || !work_dev) return fail(&g_create_err, LBM_EINVAL, "f_dev and work_dev are required");
+    if (!aligned(f_dev) || !aligned(work_dev))
+        return fail(&g_create_err, LBM_EINVAL, "device buffers must be 256-byte aligned");
+    if (cfg->use_force && !force_dev) return fail(&g_create_err, LBM_EINVAL, "use_force needs force_dev");
+    if (force_dev && !aligned(force_dev)) return fail(&g_create_err, LBM_EINVAL, "force_dev must be 256-byte aligned");
+
+    lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+    if (!ctx) return fail(&g_create_err, LBM_EDEVICE, "out of host memory");
+    ctx->cfg = *cfg;
+    ctx->f = f_dev;
+    ctx->work = static_cast<unsigned char*>(work_dev);
+    ctx->force = cfg->use_force ? force_dev : nullptr;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    Geom& g = ctx->g;
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nz = cfg->nz;
+    g.N = (long long)cfg->nx * cfg->ny * cfg->nz;
+    g.PL = (long long)cfg->ny * cfg->nz;
+    g.moving_face = -1;
+    for (int a = 0; a < 3; ++a) {
+        g.wall[a] = cfg->face[2 * a] != LBM_PERIODIC;
+        g.uw[a] = cfg->wall_u[a];
+    }
+    for (int fc = 0; fc < 6; ++fc)
+        if (cfg->face[fc] == LBM_MOVING_WALL) g.moving_face = fc;
+    g.omega = 1.0 / cfg->tau;
+
+    size_t off[5], total = 0;
+    int cap = kMaxResident;
+    if (cfg->scheme != LBM_TWO_ARRAY) {
+        // the device may hold fewer marching workgroups than the sizing bound
+        MarchPlan probe[3];
+        st = layout(*cfg, cap, probe, off, &total, &g_create_err);
+        if (st != LBM_OK) {
+            delete ctx;
+            return st;
+        }
+        for (int M = 1; M <= 2; ++M) {
+            if (probe[M].M == 0) continue;
+            const int dc = device_cap(*cfg, probe[M]);
+            if (dc <= 0) {
+                delete ctx;
+                return fail(&g_create_err, LBM_EDEVICE, "cannot query the co-residency of the marching kernel");
+            }
+            if (dc < cap) cap = dc;
+        }
+    }
+    st = layout(*cfg, cap, ctx->plan, off, &total, &g_create_err);
+    if (st != LBM_OK) {
+        delete ctx;
+        return st;
+    }
+    ctx->off_partials = off[0];
+    ctx->off_sums = off[1];
+    ctx->off_second = off[2];
+    ctx->off_flags = off[3];
+    ctx->off_side = off[4];
+    *out = ctx;
+    return LBM_OK;
+}
+
+lbm_status check_ctx(const lbm_ctx* ctx) { return ctx ? LBM_OK : LBM_ESTATE; }
+
+// records the first event of a launch pair; returns its index or -1
+long timing_begin(lbm_ctx* ctx, int steps)
+{
+    if (!ctx->timing) return -1;
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return -1;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return -1;
+        }
+        ctx->ev.push_back(a);
+        ctx->ev.push_back(b);
+    }
+    const long idx = long(ctx->ev_used);
+    if (hipEventRecord(ctx->ev[idx], ctx->stream) != hipSuccess) return -1;
+    ctx->ev_used += 2;
+    ctx->ev_steps.resize(ctx->ev_used / 2);
+    ctx->ev_steps[idx / 2] = steps;
+    return idx;
+}
+
+void timing_end(lbm_ctx* ctx, long idx)
+{
+    if (idx >= 0) (void)hipEventRecord(ctx->ev[idx + 1], ctx->stream);
+}
+
+lbm_status march_pass(lbm_ctx* ctx, int M)
+{
+    const MarchPlan& p = ctx->plan[M];
+    int* flags = reinterpret_cast<int*>(ctx->work + ctx->off_flags);
+    void* side = ctx->work + ctx->off_side;
+    lbm_status st = device_err(ctx, launch_prepass(ctx->cfg.storage, ctx->g, p, ctx->f, side, flags, ctx->stream),
+                               "prepass launch");
+    if (st != LBM_OK) return st;
+    MarchArgs a;
+    a.g = ctx->g;
+    a.f = ctx->f;
+    a.side = side;
+    a.force = ctx->force;
+    a.flags = flags;
+    a.nty = p.nty;
+    a.ntz = p.ntz;
+    a.nseg = p.nseg;
+    a.seg_len = p.seg_len;
+    a.ry = p.ry;
+    a.rz = p.rz;
+    a.xcd_remap = p.xcd_remap;
+    const bool walls = ctx->g.wall[0] || ctx->g.wall[1] || ctx->g.wall[2];
+    const bool force = ctx->force != nullptr;
+    hipError_t e;
+    const long tix = timing_begin(ctx, M);
+    switch (ctx->cfg.storage) {
+    case LBM_F64: e = launch_march_f64(walls, force, p, a, ctx->stream); break;
+    case LBM_F32: e = launch_march_f32(walls, force, p, a, ctx->stream); break;
+    case LBM_F16_OFS: e = launch_march_f16(walls, force, p, a, ctx->stream); break;
+    default: e = launch_march_bf16(walls, force, p, a, ctx->stream); break;
+    }
+    timing_end(ctx, tix);
+    return device_err(ctx, e, "marching kernel launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work_bytes)
+{
+    std::string why;
+    lbm_status st = validate(cfg, &why);
+    if (st != LBM_OK) return st;
+    MarchPlan plans[3];
+    size_t off[5], total = 0;
+    st = layout(*cfg, kMaxResident, plans, off, &total, &why);
+    if (st != LBM_OK) return st;
+    if (f_bytes) *f_bytes = size_t(19) * size_t(cfg->nx) * size_t(cfg->ny) * size_t(cfg->nz) * elem_size(cfg->storage);
+    if (work_bytes) *work_bytes = total;
+    return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev, const double* rho0_dev,
+                    const double* u0_dev, void* hip_stream, lbm_ctx** out)
+{
+    if ((rho0_dev && !aligned(rho0_dev)) || (u0_dev && !aligned(u0_dev))) {
+        if (out) *out = nullptr;
+        g_create_err = "rho0_dev and u0_dev must be 256-byte aligned";
+        return LBM_EINVAL;
+    }
+    lbm_status st = create(cfg, f_dev, work_dev, force_dev, hip_stream, out);
+    if (st != LBM_OK) return st;
+    lbm_ctx* ctx = *out;
+    st = device_err(ctx, launch_init(cfg->storage, ctx->g, ctx->f, rho0_dev, u0_dev, ctx->stream), "init launch");
+    if (st != LBM_OK) {
+        g_create_err = ctx->err;
+        delete ctx;
+        *out = nullptr;
+    }
+    return st;
+}
+
+lbm_status lbm_attach(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev, void* hip_stream,
+                      lbm_ctx** out)
+{
+    return create(cfg, f_dev, work_dev, force_dev, hip_stream, out);
+}
+
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->err.clear();
+    if (n < 0) return fail(&ctx->err, LBM_EINVAL, "n must be >= 0");
+    if (n == 0) return LBM_OK;
+    lbm_status st = LBM_OK;
+    switch (ctx->cfg.scheme) {
+    case LBM_TWO_ARRAY: {
+        void* second = ctx->work + ctx->off_second;
+        for (int64_t k = 0; k < n && st == LBM_OK; ++k) {
+            const void* src = (k & 1) ? second : ctx->f;
+            void* dst = (k & 1) ? ctx->f : second;
+            const long tix = timing_begin(ctx, 1);
+            st = device_err(ctx,
+                            launch_two_array(ctx->cfg.storage, ctx->force != nullptr, ctx->g, src, dst, ctx->force,
+                                             ctx->stream),
+                            "two-array step launch");
+            timing_end(ctx, tix);
+        }
+        if (st == LBM_OK && (n & 1))
+            st = device_err(ctx, launch_copy(ctx->cfg.storage, ctx->g, second, ctx->f, ctx->stream), "state copy");
+        break;
+    }
+    case LBM_SWAP1:
+        for (int64_t k = 0; k < n && st == LBM_OK; ++k) st = march_pass(ctx, 1);
+        break;
+    default:
+        for (int64_t k = 0; k < n / 2 && st == LBM_OK; ++k) st = march_pass(ctx, 2);
+        if (st == LBM_OK && (n & 1)) st = march_pass(ctx, 1);
+        break;
+    }
+    return st;
+}
+
+lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double* unorm_dev, double* sums_host)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->err.clear();
+    if ((rho_dev && !aligned(rho_dev)) || (u_dev && !aligned(u_dev)) || (unorm_dev && !aligned(unorm_dev)))
+        return fail(&ctx->err, LBM_EINVAL, "output buffers must be 256-byte aligned");
+    double* partials = reinterpret_cast<double*>(ctx->work + ctx->off_partials);
+    double* sums = reinterpret_cast<double*>(ctx->work + ctx->off_sums);
+    lbm_status st = device_err(ctx,
+                               launch_macro(ctx->cfg.storage, ctx->force != nullptr, ctx->g, ctx->f, ctx->force,
+                                            rho_dev, u_dev, unorm_dev, partials, sums_host ? sums : nullptr,
+                                            ctx->stream),
+                               "macroscopic launch");
+    if (st != LBM_OK || !sums_host) return st;
+    st = device_err(ctx, hipMemcpyAsync(sums_host, sums, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+                    "sums copy");
+    int timeout = 0;
+    if (st == LBM_OK && ctx->cfg.scheme != LBM_TWO_ARRAY)
+        st = device_err(ctx,
+                        hipMemcpyAsync(&timeout, ctx->work + ctx->off_flags, sizeof(int), hipMemcpyDeviceToHost,
+                                       ctx->stream),
+                        "progress-word copy");
+    if (st == LBM_OK) st = device_err(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize");
+    if (st == LBM_OK && timeout)
+        return fail(&ctx->err, LBM_EDEVICE, "a marching pass timed out waiting for a neighbouring workgroup");
+    return st;
+}
+
+lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u_dev, void* lambda_dev,
+                             void* grad_force_dev)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->err.clear();
+    if (ctx->cfg.storage != LBM_F64 && ctx->cfg.storage != LBM_F32)
+        return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for FP64 and FP32 storage only");
+    if (!f_dev || !grad_u_dev || !lambda_dev) return fail(&ctx->err, LBM_EINVAL, "f, grad_u and lambda are required");
+    if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
+    return device_err(ctx,
+                      launch_macro_adjoint(ctx->cfg.storage, ctx->force != nullptr, ctx->g, f_dev, ctx->force,
+                                           grad_u_dev, lambda_dev, grad_force_dev, ctx->stream),
+                      "adjoint seed launch");
+}
+
+lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambda_in_dev, void* lambda_out_dev,
+                            void* grad_force_dev, int32_t k)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->err.clear();
+    if (ctx->cfg.storage != LBM_F64 && ctx->cfg.storage != LBM_F32)
+        return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for FP64 and FP32 storage only");
+    if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
+    if (!f_t_dev || !lambda_in_dev || !lambda_out_dev)
+        return fail(&ctx->err, LBM_EINVAL, "f_t, lambda_in and lambda_out are required");
+    if (lambda_in_dev == lambda_out_dev) return fail(&ctx->err, LBM_EINVAL, "lambda_in and lambda_out must differ");
+    if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
+    return device_err(ctx,
+                      launch_step_adjoint(ctx->cfg.storage, ctx->force != nullptr, k, ctx->g, f_t_dev, ctx->force,
+                                          lambda_in_dev, lambda_out_dev, grad_force_dev, ctx->stream),
+                      "adjoint step launch");
+}
+
+lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->timing = enable != 0;
+    ctx->ev_used = 0;
+    ctx->ev_steps.clear();
+    return LBM_OK;
+}
+
+lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->err.clear();
+    if (!total_ms || !launches) return fail(&ctx->err, LBM_EINVAL, "total_ms and launches are required");
+    total_ms[0] = total_ms[1] = 0.0;
+    launches[0] = launches[1] = 0;
+    if (ctx->ev_used) {
+        lbm_status st = device_err(ctx, hipEventSynchronize(ctx->ev[ctx->ev_used - 1]), "event synchronize");
+        if (st != LBM_OK) return st;
+    }
+    for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+        float ms = 0.0f;
+        lbm_status st = device_err(ctx, hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]), "event elapsed time");
+        if (st != LBM_OK) return st;
+        const int k = ctx->ev_steps[i / 2] == 2 ? 1 : 0;
+        total_ms[k] += ms;
+        launches[k] += 1;
+    }
+    ctx->ev_used = 0;
+    ctx->ev_steps.clear();
+    return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx)
+{
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+void lbm_destroy(lbm_ctx* ctx) { delete ctx; }
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// lbm_internal.hpp -- argument blocks and launcher declarations shared by the
+// HIP kernels and the C-ABI implementation.  Nothing here is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Geometry and physics common to every kernel.
+struct Geom {
+    int nx, ny, nz;
+    long long N;      // nx*ny*nz
+    long long PL;     // ny*nz, cells per x-plane
+    int wall[3];      // 1 if the axis has walls (0: periodic)
+    int moving_face;  // -1 or 0..5 (-x,+x,-y,+y,-z,+z)
+    double uw[3];     // moving-face velocity
+    double omega;     // 1/tau
+};
+
+// One in-place marching pass (M = steps merged per pass).
+struct MarchPlan {
+    int M = 0;
+    int TY = 0, TZ = 0, NT = 0;  // interior tile and threads per workgroup
+    int nty = 0, ntz = 0;        // tiles along y and z
+    int nseg = 0, seg_len = 0;   // x segments
+    int ry = 1, rz = 1;          // neighbourhood radius (in tiles) of the hazard check
+    int blocks = 0;              // nty*ntz*nseg work items, all co-resident
+    int xcd_remap = 0;           // map consecutive work items onto one XCD
+    size_t side_bytes = 0;       // side planes: nseg * M planes * 19 values
+    size_t flag_bytes = 0;       // one int per work item
+};
+
+struct MarchArgs {
+    Geom g;
+    void* f;            // distributions, in place
+    void* side;         // time-t copies of the first M planes of every segment
+    const void* force;  // 3N or null
+    int* flags;         // progress (planes loaded) of every work item
+    int nty, ntz, nseg, seg_len, ry, rz, xcd_remap;
+};
+
+// Launchers; each returns the hipError_t of its launch.
+hipError_t launch_init(int storage, const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s);
+hipError_t launch_two_array(int storage, bool force, const Geom& g, const void* src, void* dst, const void* F,
+                            hipStream_t s);
+hipError_t launch_copy(int storage, const Geom& g, const void* src, void* dst, hipStream_t s);
+hipError_t launch_prepass(int storage, const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags,
+                          hipStream_t s);
+
+constexpr int SUM_BLOCKS = 1024;  // fixed grid of the reduction: deterministic order
+hipError_t launch_macro(int storage, bool force, const Geom& g, const void* f, const void* F, double* rho, double* u,
+                        double* unorm, double* partials, double* sums, hipStream_t s);
+hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const void* f, const void* F,
+                                const void* grad_u, void* lambda, void* grad_force, hipStream_t s);
+hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, const void* f_t, const void* F,
+                               const void* lam_in, void* lam_out, void* grad_force, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,433 @@
+// march.hpp -- the in-place, single-copy D3Q19 update with M in {1, 2} time
+// steps merged per pass over HBM (the paper's Fuse Swap LBM of Sec. 3 /
+// Alg. 1 for M = 1, and its two-step merging of Sec. 4.1 / Alg. 2 for M = 2),
+// designed for CDNA4 rather than transcribed from the CPU algorithms.
+//
+// Decomposition.  The y-z plane is cut into TY x TZ tiles and the x axis into
+// segments; one workgroup owns a (tile, segment) work item and marches along
+// x, one plane per iteration.  It loads the time-t plane of its tile plus a
+// halo of M cells (all 19 populations, straight from the single copy),
+// collides it, and exchanges the populations that move in y or z through LDS;
+// populations that move only in x stay in the thread's registers and reach
+// their plane one iteration later or earlier.  For M = 2 the second step runs
+// one plane behind the first on the tile plus a halo of one cell, so the t+1
+// state never leaves the chip (the dependency cone of Sec. 4.1: the second
+// computation of a cell follows the first of its later neighbours).  The
+// finished t+M plane, M planes behind the load front, is written back in
+// place over the time-t plane it replaces: there is no second lattice.
+//
+// In-place hazards across workgroups (the GPU form of the thread-safety
+// argument of Sec. 4.2).  A workgroup may overwrite plane r only after every
+// workgroup whose halo covers its tile has loaded plane r.  Each work item
+// publishes its load front in a progress counter (agent-scope atomic); before
+// a store, one wave polls the counters of the neighbouring tiles (and, for the
+// last M planes of a segment, of the next segment, whose first loads reach
+// back M planes).  All work items are co-resident (cooperative launch), and
+// the one with the smallest load front never waits, so the march cannot
+// deadlock; every wait is additionally bounded and reports a timeout.
+// The first M planes of every segment are read by the previous segment at
+// its end, after they were overwritten; a prepass saves their time-t copies
+// (the analogue of the bounding-box pre-processing of Alg. 1's Stage I).
+//
+// Boundaries.  Periodic axes wrap indices.  A population whose source lies
+// beyond a wall is the cell's own reversed post-collision value (halfway
+// bounce-back, what the swap algorithm leaves in slots without a partner),
+// plus 6 w_q (c_q . u_w) if the moving face is among the faces crossed.
+#pragma once
+
+#include "d3q19.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// direction masks: bit q set for every q with c_x = +1 / -1
+__host__ __device__ constexpr uint32_t mask_cx(int sgn)
+{
+    uint32_t m = 0;
+    for (int q = 0; q < Q; ++q)
+        if (cxq(q) == sgn) m |= 1u << q;
+    return m;
+}
+
+__device__ __forceinline__ int wrapi(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Receive of one level for one column.  The level has just collided plane p:
+// the post-collision values of the column-moving directions are in X
+// (16 rows of `stride` columns; this column at index ci, row pitch wz), the
+// three x-only directions (q = 0, 1, 10) in o0, o1, o10.  Completes plane p-1
+// into out[] and deposits the values destined for planes p and p+1 in acc[]
+// and nxt[].  bdone / bnext: directions whose source is beyond a wall for
+// planes p-1 / p; mnext: those among bnext that cross the moving face.
+template <class R, bool WALLS>
+__device__ __forceinline__ void receive(R (&acc)[Q], R (&nxt)[5], R (&out)[Q], const R* __restrict__ X, int stride,
+                                        int ci, int wz, R o0, R o1, R o10, uint32_t bdone, uint32_t bnext,
+                                        uint32_t mnext, R uwx, R uwy, R uwz)
+{
+    // completion of plane p-1: its c_x = -1 populations come from plane p
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (cxq(q) == -1) {
+            R rv;
+            if constexpr (moves_yz(q))
+                rv = X[yz_index(q) * stride + ci - cyq(q) * wz - czq(q)];
+            else
+                rv = o1;
+            if constexpr (WALLS)
+                out[q] = ((bdone >> q) & 1u) ? acc[q] : rv;
+            else
+                out[q] = rv;
+        } else {
+            out[q] = acc[q];
+        }
+    });
+    // deposits for planes p (c_x = 0 and bounce-backs) and p+1 (c_x = +1)
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int qo = oppq(q);
+        R bval = R(0);
+        if constexpr (WALLS && q != 0) {
+            if constexpr (moves_yz(qo))
+                bval = X[yz_index(qo) * stride + ci];
+            else
+                bval = (qo == 1) ? o1 : o10;
+            if ((mnext >> q) & 1u) bval += wall_term<q>(uwx, uwy, uwz);
+        }
+        if constexpr (cxq(q) == 0) {
+            R rv;
+            if constexpr (q == 0)
+                rv = o0;
+            else
+                rv = X[yz_index(q) * stride + ci - cyq(q) * wz - czq(q)];
+            if constexpr (WALLS && q != 0)
+                acc[q] = ((bnext >> q) & 1u) ? bval : rv;
+            else
+                acc[q] = rv;
+        } else if constexpr (cxq(q) == 1) {
+            constexpr int j = xp_index(q);
+            if constexpr (WALLS)
+                acc[q] = ((bnext >> q) & 1u) ? bval : nxt[j];
+            else
+                acc[q] = nxt[j];
+            if constexpr (moves_yz(q))
+                nxt[j] = X[yz_index(q) * stride + ci - cyq(q) * wz - czq(q)];
+            else
+                nxt[j] = o10;
+        } else {
+            if constexpr (WALLS) acc[q] = bval;
+        }
+    });
+}
+
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(NT) void k_march(MarchArgs a)
+{
+    using Cd = Codec<S>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    constexpr int WY = TY + 2 * M, WZ = TZ + 2 * M, NC = WY * WZ;
+    constexpr int K = (NC + NT - 1) / NT;
+    constexpr int WZ2 = TZ + 2, NC2 = (TY + 2) * WZ2;
+    constexpr int NB1 = (M == 1) ? 2 : 1;  // a single exchange level is double-buffered
+    constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
+    static_assert(M == 1 || M == 2, "one or two merged steps");
+
+    __shared__ R X1[NB1][16 * NC];
+    __shared__ R X2[(M == 2) ? 16 * NC2 : 1];
+
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+    int wid = blockIdx.x;
+    if (a.xcd_remap) {
+        const int per = gridDim.x >> 3;
+        wid = (wid & 7) * per + (wid >> 3);
+    }
+    const int tz = wid % a.ntz, ty = (wid / a.ntz) % a.nty, seg = wid / (a.ntz * a.nty);
+    const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
+    const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);
+    const bool wallx = g.wall[0] != 0;
+    const bool has_next = !wallx || seg + 1 < a.nseg;
+    const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
+    const R omega = R(g.omega);
+    const R uwx = R(g.uw[0]), uwy = R(g.uw[1]), uwz = R(g.uw[2]);
+    const long long N = g.N, PL = g.PL;
+
+    // ---- columns owned by this thread ----
+    int gofs[K], rad[K], ci2[K];
+    uint32_t byz[K], myz[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gofs[k] = -1;
+        rad[k] = M + 1;
+        ci2[k] = 0;
+        byz[k] = 0;
+        myz[k] = 0;
+        const int c = tid + k * NT;
+        if (c < NC) {
+            const int ly = c / WZ, lz = c - (c / WZ) * WZ;
+            if (ly < TYe + 2 * M && lz < TZe + 2 * M) {
+                const int dy = ly < M ? M - ly : (ly >= M + TYe ? ly - (M + TYe) + 1 : 0);
+                const int dz = lz < M ? M - lz : (lz >= M + TZe ? lz - (M + TZe) + 1 : 0);
+                int y = ty * TY - M + ly, z = tz * TZ - M + lz;
+                bool inside = true;
+                if (g.wall[1]) inside = inside && y >= 0 && y < g.ny;
+                else y = wrapi(y, g.ny);
+                if (g.wall[2]) inside = inside && z >= 0 && z < g.nz;
+                else z = wrapi(z, g.nz);
+                if (inside) {
+                    gofs[k] = y * g.nz + z;
+                    rad[k] = dy > dz ? dy : dz;
+                    ci2[k] = (ly - 1) * WZ2 + (lz - 1);
+                    if constexpr (WALLS) {
+                        uint32_t b = 0, mv = 0;
+                        sfor<1, Q>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            if constexpr (moves_yz(q)) {
+                                const int ys = y - cyq(q), zs = z - czq(q);
+                                int f1 = -1, f2 = -1;
+                                if (g.wall[1] && ys < 0) f1 = 2;
+                                if (g.wall[1] && ys >= g.ny) f1 = 3;
+                                if (g.wall[2] && zs < 0) f2 = 4;
+                                if (g.wall[2] && zs >= g.nz) f2 = 5;
+                                if (f1 >= 0 || f2 >= 0) b |= 1u << q;
+                                if (g.moving_face >= 0 && (f1 == g.moving_face || f2 == g.moving_face)) mv |= 1u << q;
+                            }
+                        });
+                        byz[k] = b;
+                        myz[k] = mv;
+                    }
+                }
+            }
+        }
+    }
+
+    // x-wall bounce-back and moving-face masks of a plane
+    auto xb = [&](int p) -> uint32_t {
+        if (!wallx) return 0u;
+        return (p == 0 ? CXP : 0u) | (p == g.nx - 1 ? CXM : 0u);
+    };
+    auto xm = [&](int p) -> uint32_t {
+        if (!wallx) return 0u;
+        return ((p == 0 && g.moving_face == 0) ? CXP : 0u) | ((p == g.nx - 1 && g.moving_face == 1) ? CXM : 0u);
+    };
+    auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
+
+    // ---- pipeline registers ----
+    T Lr[K][Q];
+    R Fl1[K][3], Fl2[K][3];
+    R acc1[K][Q], nxt1[K][5], acc2[K][Q], nxt2[K][5];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Lr[k][q] = T(0);
+            acc1[k][q] = R(0);
+            acc2[k][q] = R(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            nxt1[k][j] = R(0);
+            nxt2[k][j] = R(0);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fl1[k][c] = R(0);
+            Fl2[k][c] = R(0);
+        }
+    }
+
+    T* __restrict__ f = static_cast<T*>(a.f);
+    const T* __restrict__ side = static_cast<const T*>(a.side);
+    const R* __restrict__ F = static_cast<const R*>(a.force);
+
+    auto issue_load = [&](int xp) {
+        if (!present(xp)) return;
+        const bool from_side = xp >= e && has_next;
+        const int px = wrapi(xp, g.nx);
+        const T* base;
+        long long qstride;
+        if (from_side) {
+            base = side + ((long long)(nseg_next * M + (xp - e)) * Q) * PL;
+            qstride = PL;
+        } else {
+            base = f + (long long)px * PL;
+            qstride = N;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (rad[k] <= M && gofs[k] >= 0) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) Lr[k][q] = base[q * qstride + gofs[k]];
+                if constexpr (FORCE) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Fl1[k][c] = F[c * N + (long long)px * PL + gofs[k]];
+                }
+            }
+        }
+    };
+
+    auto poll = [&](int i, int r) {
+        if (tid >= 64) return;
+        const int nnz = 2 * a.rz + 1, n1 = (2 * a.ry + 1) * nnz;
+        int lane = tid, sg = seg, need = 0;
+        if (lane >= n1) {
+            if (!(has_next && r >= e - M)) return;
+            lane -= n1;
+            if (lane >= n1) return;
+            sg = nseg_next;
+            need = r - e + M + 1;
+        } else {
+            need = i - M + 1;
+        }
+        int yy = ty + lane / nnz - a.ry, zz = tz + lane % nnz - a.rz;
+        if (g.wall[1]) {
+            if (yy < 0 || yy >= a.nty) return;
+        } else {
+            yy = wrapi(yy, a.nty);
+        }
+        if (g.wall[2]) {
+            if (zz < 0 || zz >= a.ntz) return;
+        } else {
+            zz = wrapi(zz, a.ntz);
+        }
+        const int* fl = a.flags + 1 + ((long long)sg * a.nty + yy) * a.ntz + zz;
+        // bounded wait: a timeout is recorded in flags[0] and the march goes on
+        for (int spin = 0; spin < (1 << 22); ++spin) {
+            if (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+
+    auto store = [&](const R (&out)[Q], int k, int r) {
+        T* base = f + (long long)r * PL + gofs[k];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) base[q * N] = Cd::enc(out[q]);
+    };
+
+    const int total = (e - s) + 2 * M;
+    issue_load(s - M);
+    for (int i = 0; i < total; ++i) {
+        const int xl = s - M + i;
+        const int buf = (M == 1) ? (i & 1) : 0;
+        const int r_out = xl - M;
+        const bool storing = r_out >= s && r_out < e;
+        R* X1b = X1[buf];
+
+        // ---- step 1: collide plane xl on the tile plus M halo cells ----
+        R o1[K][3];
+        if (present(xl)) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                o1[k][0] = o1[k][1] = o1[k][2] = R(0);
+                if (rad[k] <= M && gofs[k] >= 0) {
+                    R v[Q];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
+                    collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+                    const int c = tid + k * NT;
+                    sfor<0, Q>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        if constexpr (moves_yz(q)) X1b[yz_index(q) * NC + c] = v[q];
+                    });
+                    o1[k][0] = v[0];
+                    o1[k][1] = v[1];
+                    o1[k][2] = v[10];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) o1[k][0] = o1[k][1] = o1[k][2] = R(0);
+        }
+        R Fs[K][3];
+        if constexpr (FORCE) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
+        }
+        if (i + 1 < total) issue_load(xl + 1);
+        if (M == 1 && storing) poll(i, r_out);
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(a.flags + 1 + wid, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+        // ---- receive step 1 on the tile plus M-1 halo cells: completes plane xl-1 ----
+        const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
+        R o2[K][3];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            o2[k][0] = o2[k][1] = o2[k][2] = R(0);
+            if (rad[k] <= M - 1 && gofs[k] >= 0) {
+                R out[Q];
+                receive<R, WALLS>(acc1[k], nxt1[k], out, X1b, NC, tid + k * NT, WZ, o1[k][0], o1[k][1], o1[k][2],
+                                  byz[k] | xbd1, byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
+                if constexpr (M == 1) {
+                    if (storing) store(out, k, r_out);
+                } else {
+                    // ---- step 2: collide plane xl-1 on the tile plus one halo cell ----
+                    if (i >= M && present(xl - 1)) {
+                        collide<R, FORCE>(out, omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        sfor<0, Q>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = out[q];
+                        });
+                        o2[k][0] = out[0];
+                        o2[k][1] = out[1];
+                        o2[k][2] = out[10];
+                    }
+                }
+            }
+        }
+        if constexpr (M == 2) {
+            if constexpr (FORCE) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Fl2[k][c] = Fs[k][c];
+            }
+            if (storing) poll(i, r_out);
+            __syncthreads();
+            // ---- receive step 2 on the tile: completes plane xl-2, written in place ----
+            if (i >= M) {
+                const uint32_t xbd2 = xb(xl - 2), xbn2 = xb(xl - 1), xmn2 = xm(xl - 1);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (rad[k] == 0 && gofs[k] >= 0) {
+                        R out[Q];
+                        receive<R, WALLS>(acc2[k], nxt2[k], out, X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
+                                          byz[k] | xbd2, byz[k] | xbn2, myz[k] | xmn2, uwx, uwy, uwz);
+                        if (storing) store(out, k, r_out);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Launch of one compiled shape.  Cooperative launch guarantees co-residency
+// of all work items (required by the progress-counter protocol).
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+hipError_t launch_march_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
+{
+    auto kern = k_march<S, M, TY, TZ, NT, WALLS, FORCE>;
+    MarchArgs arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks), dim3(NT), params, 0, st);
+}
+
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+int max_blocks_shape()
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<S, M, TY, TZ, NT, WALLS, FORCE>, NT, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+}  // namespace lbm

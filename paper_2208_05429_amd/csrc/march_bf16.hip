@@ -1,0 +1,15 @@
+// march_bf16.hip -- marching-kernel instantiations for this storage type.
+#include "march_dispatch.hpp"
+
+namespace lbm {
+
+using List_bf16 = ShapeList<Shape<ST_BF16, 2, 32, 32, 512, false>, Shape<ST_BF16, 1, 32, 32, 512, false>>;
+
+hipError_t launch_march_bf16(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+{
+    return List_bf16::launch(walls, force, p, a, s);
+}
+
+int max_blocks_bf16(bool walls, bool force, const MarchPlan& p) { return List_bf16::max_blocks(walls, force, p); }
+
+}  // namespace lbm

@@ -1,0 +1,74 @@
+// march_dispatch.hpp -- compiled shapes of the marching kernel and their
+// dispatch from a runtime plan.  Each storage type instantiates its own list
+// in its own translation unit (march_<type>.hip).
+#pragma once
+
+#include "march.hpp"
+
+namespace lbm {
+
+template <int S, int M, int TY, int TZ, int NT, bool ALLOW_FORCE>
+struct Shape {
+    static bool match(const MarchPlan& p) { return p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT; }
+    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        if constexpr (ALLOW_FORCE) {
+            if (force)
+                return walls ? launch_march_shape<S, M, TY, TZ, NT, true, true>(p, a, s)
+                             : launch_march_shape<S, M, TY, TZ, NT, false, true>(p, a, s);
+        } else {
+            if (force) return hipErrorInvalidValue;
+        }
+        return walls ? launch_march_shape<S, M, TY, TZ, NT, true, false>(p, a, s)
+                     : launch_march_shape<S, M, TY, TZ, NT, false, false>(p, a, s);
+    }
+    static int max_blocks(bool walls, bool force)
+    {
+        if constexpr (ALLOW_FORCE) {
+            if (force)
+                return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, true>()
+                             : max_blocks_shape<S, M, TY, TZ, NT, false, true>();
+        } else {
+            if (force) return 0;
+        }
+        return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, false>()
+                     : max_blocks_shape<S, M, TY, TZ, NT, false, false>();
+    }
+};
+
+template <class... Shapes>
+struct ShapeList {
+    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        hipError_t r = hipErrorInvalidValue;
+        bool done = false;
+        ((!done && Shapes::match(p) ? (r = Shapes::launch(walls, force, p, a, s), done = true) : false), ...);
+        return r;
+    }
+    static int max_blocks(bool walls, bool force, const MarchPlan& p)
+    {
+        int r = 0;
+        bool done = false;
+        ((!done && Shapes::match(p) ? (r = Shapes::max_blocks(walls, force), done = true) : false), ...);
+        return r;
+    }
+};
+
+// Shapes per storage type, {M, TY, TZ, NT}, in variant order (variant v uses
+// entries 2v (M = 2) and 2v+1 (M = 1)).
+struct ShapeEntry {
+    int M, TY, TZ, NT;
+};
+constexpr ShapeEntry kShapesF64[] = {{2, 12, 28, 512}, {1, 14, 30, 512}};
+constexpr ShapeEntry kShapesF32[] = {{2, 32, 32, 512}, {1, 32, 32, 512}};
+
+hipError_t launch_march_f64(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
+hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
+hipError_t launch_march_f16(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
+hipError_t launch_march_bf16(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
+int max_blocks_f64(bool walls, bool force, const MarchPlan& p);
+int max_blocks_f32(bool walls, bool force, const MarchPlan& p);
+int max_blocks_f16(bool walls, bool force, const MarchPlan& p);
+int max_blocks_bf16(bool walls, bool force, const MarchPlan& p);
+
+}  // namespace lbm

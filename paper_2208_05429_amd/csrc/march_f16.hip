@@ -1,0 +1,15 @@
+// march_f16.hip -- marching-kernel instantiations for this storage type.
+#include "march_dispatch.hpp"
+
+namespace lbm {
+
+using List_f16 = ShapeList<Shape<ST_F16, 2, 32, 32, 512, false>, Shape<ST_F16, 1, 32, 32, 512, false>>;
+
+hipError_t launch_march_f16(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+{
+    return List_f16::launch(walls, force, p, a, s);
+}
+
+int max_blocks_f16(bool walls, bool force, const MarchPlan& p) { return List_f16::max_blocks(walls, force, p); }
+
+}  // namespace lbm

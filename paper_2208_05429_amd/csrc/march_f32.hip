@@ -1,0 +1,15 @@
+// march_f32.hip -- marching-kernel instantiations for this storage type.
+#include "march_dispatch.hpp"
+
+namespace lbm {
+
+using List_f32 = ShapeList<Shape<ST_F32, 2, 32, 32, 512, true>, Shape<ST_F32, 1, 32, 32, 512, true>>;
+
+hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+{
+    return List_f32::launch(walls, force, p, a, s);
+}
+
+int max_blocks_f32(bool walls, bool force, const MarchPlan& p) { return List_f32::max_blocks(walls, force, p); }
+
+}  // namespace lbm

@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/lbm.h declares, and rejects bad arguments with the
+documented status codes before touching the device."""
+import ctypes
+
+import pytest
+
+from paper_2208_05429_amd import capi
+
+
+def test_library_exports_every_declared_function():
+    L = capi.lib()
+    names = capi.header_functions()
+    assert set(names) >= {"lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_macroscopic",
+                          "lbm_macro_adjoint", "lbm_step_adjoint", "lbm_set_stream", "lbm_last_error", "lbm_destroy"}
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _cfg(**kw):
+    base = dict(shape=(32, 32, 32), tau=0.8, storage=capi.LBM_F32, scheme=capi.LBM_SWAP2)
+    base.update(kw)
+    return capi.make_config(**base)
+
+
+def _status(cfg):
+    f = ctypes.c_size_t(0)
+    w = ctypes.c_size_t(0)
+    return capi.lib().lbm_buffer_sizes(ctypes.byref(cfg), ctypes.byref(f), ctypes.byref(w)), f.value, w.value
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau=0.5), capi.LBM_EINVAL),
+    (dict(tau=float("nan")), capi.LBM_EINVAL),
+    (dict(shape=(0, 4, 4)), capi.LBM_EINVAL),
+    (dict(storage=7), capi.LBM_EINVAL),
+    (dict(scheme=5), capi.LBM_EINVAL),
+    (dict(faces=(capi.LBM_WALL, capi.LBM_PERIODIC, 0, 0, 0, 0)), capi.LBM_EINVAL),
+    (dict(faces=(capi.LBM_MOVING_WALL, capi.LBM_MOVING_WALL, 0, 0, 0, 0)), capi.LBM_EINVAL),
+    (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
+    (dict(storage=capi.LBM_F16_OFS, use_force=True), capi.LBM_EUNSUPPORTED),
+    (dict(variant=99), capi.LBM_EUNSUPPORTED),
+    (dict(shape=(64, 1024, 1024)), capi.LBM_EUNSUPPORTED),
+])
+def test_invalid_configs_are_rejected(kw, code):
+    assert _status(_cfg(**kw))[0] == code
+
+
+def test_buffer_sizes():
+    for storage, s in ((capi.LBM_F64, 8), (capi.LBM_F32, 4), (capi.LBM_F16_OFS, 2), (capi.LBM_BF16_OFS, 2)):
+        st, fb, wb = _status(_cfg(storage=storage))
+        assert st == capi.LBM_OK and fb == 19 * 32 ** 3 * s and wb > 0
+    st, fb, wb = _status(_cfg(scheme=capi.LBM_TWO_ARRAY))
+    assert st == capi.LBM_OK and wb >= fb  # the plain scheme's second lattice lives in the work buffer
+    st, fb, wb2 = _status(_cfg(scheme=capi.LBM_SWAP2))
+    assert wb2 < fb  # single copy: the work buffer is a small fraction of the lattice
+    assert _status(_cfg(shape=(512, 512, 512)))[0] == capi.LBM_OK
+
+
+def test_null_and_state_errors():
+    L = capi.lib()
+    cfg = _cfg()
+    out = ctypes.c_void_p(1)
+    st = L.lbm_init(ctypes.byref(cfg), None, None, None, None, None, None, ctypes.byref(out))
+    assert st == capi.LBM_EINVAL and not out.value
+    assert "required" in capi.lbm_last_error(None)
+    st = L.lbm_init(ctypes.byref(cfg), ctypes.c_void_p(256 * 3 + 8), ctypes.c_void_p(512), None, None, None, None,
+                    ctypes.byref(out))
+    assert st == capi.LBM_EINVAL and "aligned" in capi.lbm_last_error(None)
+    cfg_f = _cfg(use_force=True)
+    st = L.lbm_init(ctypes.byref(cfg_f), ctypes.c_void_p(256), ctypes.c_void_p(512), None, None, None, None,
+                    ctypes.byref(out))
+    assert st == capi.LBM_EINVAL
+    assert L.lbm_step(None, 1) == capi.LBM_ESTATE
+    assert L.lbm_macroscopic(None, None, None, None, None) == capi.LBM_ESTATE
+    assert L.lbm_step_adjoint(None, None, None, None, None, 1) == capi.LBM_ESTATE
+    assert L.lbm_set_stream(None, None) == capi.LBM_ESTATE
+    L.lbm_destroy(None)

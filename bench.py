@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also run one device-to-device copy of BYTES bytes (counter calibration)")
     return ap.parse_args()
 
 
@@ -166,6 +168,19 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "conservation": {"mass": sums[0], "momentum": list(sums[1:])},
     }
+    if a.copy_probe:
+        src = torch.empty(a.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        dst.copy_(src)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1)
+        out["copy_probe"] = {"bytes": a.copy_probe, "ms": round(cms, 4),
+                             "GB/s (read+write)": round(2 * a.copy_probe / (cms * 1e-3) / 1e9, 1)}
+        del src, dst
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)

@@ -64,6 +64,58 @@ __device__ __forceinline__ void sfor(F&& f)
     }
 }
 
+// ---- buffer access: uniform descriptor + 32-bit per-lane byte offset ----
+// One descriptor covers `bytes` bytes from `base`; lanes whose offset is out of
+// range read zero and their stores are dropped by the hardware range check.
+constexpr int kBufDword3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+constexpr uint32_t kOffNone = 0xffffffffu;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufDword3);
+}
+
+template <class T>
+struct Buf;
+template <>
+struct Buf<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+    }
+};
+template <>
+struct Buf<double> {
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return __hiloint2double(int(v[1]), int(v[0]));
+    }
+    static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        u2 w;
+        w[0] = uint32_t(__double2loint(v));
+        w[1] = uint32_t(__double2hiint(v));
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+    }
+};
+template <>
+struct Buf<uint16_t> {
+    static __device__ __forceinline__ uint16_t ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void st(uint16_t v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+    }
+};
+
 // ---- storage codecs: stored value is g = f - w_q ----
 enum : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
 

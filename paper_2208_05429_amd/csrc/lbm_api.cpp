@@ -52,16 +52,20 @@ lbm_status fail(std::string* where, lbm_status st, const std::string& msg)
     return st;
 }
 
-bool march_shape_of(int storage, int M, int variant, int* TY, int* TZ, int* NT)
+bool march_shape_of(int storage, int M, int variant, int nz, MarchPlan* r)
 {
     const ShapeEntry* tab = storage == LBM_F64 ? kShapesF64 : kShapesF32;
     const int n = storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
                                      : int(sizeof(kShapesF32) / sizeof(ShapeEntry));
-    const int idx = 2 * variant + (M == 2 ? 0 : 1);
+    int idx = 2 * variant + (M == 2 ? 0 : 1);
     if (variant < 0 || idx >= n || tab[idx].M != M) return false;
-    *TY = tab[idx].TY;
-    *TZ = tab[idx].TZ;
-    *NT = tab[idx].NT;
+    // pairs of z-adjacent cells need an even row length: use the next (plain) entry
+    if (tab[idx].pr && (nz % 2) != 0) idx += 2;
+    if (idx >= n || tab[idx].M != M) return false;
+    r->TY = tab[idx].TY;
+    r->TZ = tab[idx].TZ;
+    r->NT = tab[idx].NT;
+    r->pr = tab[idx].pr;
     return true;
 }
 
@@ -70,7 +74,7 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
 {
     MarchPlan r;
     r.M = M;
-    if (!march_shape_of(c.storage, M, c.variant, &r.TY, &r.TZ, &r.NT))
+    if (!march_shape_of(c.storage, M, c.variant, c.nz, &r))
         return fail(why, LBM_EUNSUPPORTED, "no compiled marching kernel for this storage/variant");
     r.nty = (c.ny + r.TY - 1) / r.TY;
     r.ntz = (c.nz + r.TZ - 1) / r.TZ;

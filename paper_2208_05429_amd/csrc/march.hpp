@@ -55,19 +55,19 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-// Receive of one level for one column.  The level has just collided plane p:
-// the post-collision values of the column-moving directions are in X
-// (16 rows of `stride` columns; this column at index ci, row pitch wz), the
-// three x-only directions (q = 0, 1, 10) in o0, o1, o10.  Completes plane p-1
-// into out[] and deposits the values destined for planes p and p+1 in acc[]
-// and nxt[].  bdone / bnext: directions whose source is beyond a wall for
-// planes p-1 / p; mnext: those among bnext that cross the moving face.
+// The two halves of one level's exchange for one column.  The level has just
+// collided plane p: the post-collision values of the column-moving
+// directions are in X (16 rows of `stride` columns; this column at index ci,
+// row pitch wz), the three x-only directions (q = 0, 1, 10) in o0, o1, o10.
+//
+// complete(): acc[] holds plane p-1 except its c_x = -1 populations, which
+// come from plane p; afterwards acc[] is the whole plane p-1 (at the level's
+// output time).  bdone: directions of plane p-1 whose source is beyond a wall
+// (their value was deposited earlier).
 template <class R, bool WALLS>
-__device__ __forceinline__ void receive(R (&acc)[Q], R (&nxt)[5], R (&out)[Q], const R* __restrict__ X, int stride,
-                                        int ci, int wz, R o0, R o1, R o10, uint32_t bdone, uint32_t bnext,
-                                        uint32_t mnext, R uwx, R uwy, R uwz)
+__device__ __forceinline__ void complete(R (&acc)[Q], const R* __restrict__ X, int stride, int ci, int wz, R o1,
+                                         uint32_t bdone)
 {
-    // completion of plane p-1: its c_x = -1 populations come from plane p
     sfor<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (cxq(q) == -1) {
@@ -77,14 +77,23 @@ __device__ __forceinline__ void receive(R (&acc)[Q], R (&nxt)[5], R (&out)[Q], c
             else
                 rv = o1;
             if constexpr (WALLS)
-                out[q] = ((bdone >> q) & 1u) ? acc[q] : rv;
+                acc[q] = ((bdone >> q) & 1u) ? acc[q] : rv;
             else
-                out[q] = rv;
-        } else {
-            out[q] = acc[q];
+                acc[q] = rv;
         }
     });
-    // deposits for planes p (c_x = 0 and bounce-backs) and p+1 (c_x = +1)
+}
+
+// deposit(): after acc[] was consumed, refill it with what is known of plane
+// p (c_x = 0 populations, bounce-backs, and the c_x = +1 populations received
+// one iteration earlier in nxt[]) and put plane p+1's c_x = +1 populations in
+// nxt[].  bnext: directions of plane p whose source is beyond a wall; mnext:
+// those among them that cross the moving face.
+template <class R, bool WALLS>
+__device__ __forceinline__ void deposit(R (&acc)[Q], R (&nxt)[5], const R* __restrict__ X, int stride, int ci,
+                                        int wz, R o0, R o1, R o10, uint32_t bnext, uint32_t mnext, R uwx, R uwy,
+                                        R uwz)
+{
     sfor<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int qo = oppq(q);
@@ -157,10 +166,15 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
     // ---- columns owned by this thread ----
     int gofs[K], rad[K], ci2[K];
+    uint32_t voff[K];   // byte offset of the column within one direction's plane
+    uint32_t loff[K];   // voff for columns that load (tile plus M halo cells), else out of range
+    uint32_t loffR[K];  // the same in units of the arithmetic type (force field)
+    uint32_t soff[K];   // voff for interior columns (stored), else out of range
     uint32_t byz[K], myz[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         gofs[k] = -1;
+        voff[k] = kOffNone;
         rad[k] = M + 1;
         ci2[k] = 0;
         byz[k] = 0;
@@ -179,6 +193,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                 else z = wrapi(z, g.nz);
                 if (inside) {
                     gofs[k] = y * g.nz + z;
+                    voff[k] = uint32_t(gofs[k]) * uint32_t(sizeof(T));
                     rad[k] = dy > dz ? dy : dz;
                     ci2[k] = (ly - 1) * WZ2 + (lz - 1);
                     if constexpr (WALLS) {
@@ -202,6 +217,14 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                 }
             }
         }
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const bool loads = rad[k] <= M && gofs[k] >= 0;
+        loff[k] = loads ? voff[k] : kOffNone;
+        loffR[k] = loads ? uint32_t(gofs[k]) * uint32_t(sizeof(R)) : kOffNone;
+        soff[k] = (rad[k] == 0 && gofs[k] >= 0) ? voff[k] : kOffNone;
     }
 
     // x-wall bounce-back and moving-face masks of a plane
@@ -243,8 +266,16 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     const T* __restrict__ side = static_cast<const T*>(a.side);
     const R* __restrict__ F = static_cast<const R*>(a.force);
 
-    auto issue_load = [&](int xp) {
-        if (!present(xp)) return;
+    // Loads and stores address one direction of one plane through a buffer
+    // descriptor built on the scalar unit plus a 32-bit per-lane byte offset;
+    // unused slots carry an out-of-range offset and touch no memory.
+    const uint32_t plane_bytes = uint32_t(PL) * uint32_t(sizeof(T));
+    // Every iteration issues the same loads, unconditionally: a plane that is
+    // absent (beyond a wall) or past the end of the march gets an empty buffer
+    // range, so the hardware returns zeros without touching memory.  Uniform
+    // issue keeps the compiler's count of outstanding memory operations exact.
+    auto issue_load_slot = [&](int xp, bool wanted, int k) {
+        const bool live = wanted && present(xp);
         const bool from_side = xp >= e && has_next;
         const int px = wrapi(xp, g.nx);
         const T* base;
@@ -256,153 +287,210 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             base = f + (long long)px * PL;
             qstride = N;
         }
+        const uint32_t range = live ? plane_bytes : 0u;
+        const T* bq = base;  // running pointer: nothing per direction stays live across iterations
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (rad[k] <= M && gofs[k] >= 0) {
+        for (int q = 0; q < Q; ++q) {
+            Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), loff[k]);
+            bq += qstride;
+        }
+        if constexpr (FORCE) {
+            const uint32_t rangeR = live ? uint32_t(PL) * uint32_t(sizeof(R)) : 0u;
+            const R* bc = F + (long long)px * PL;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) Lr[k][q] = base[q * qstride + gofs[k]];
-                if constexpr (FORCE) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) Fl1[k][c] = F[c * N + (long long)px * PL + gofs[k]];
-                }
+            for (int c = 0; c < 3; ++c) {
+                Fl1[k][c] = Buf<R>::ld(make_rsrc(bc, rangeR), loffR[k]);
+                bc += N;
             }
         }
     };
+    auto issue_load = [&](int xp, bool wanted) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) issue_load_slot(xp, wanted, k);
+    };
 
-    auto poll = [&](int i, int r) {
-        if (tid >= 64) return;
+    // Hazard check.  Every wave watches the progress counters itself, one per
+    // lane: lanes [0, n1) the tiles around this one in the same segment, lanes
+    // [n1, 2 n1) the same tiles in the next segment, whose first M loads reach
+    // back into this one.  The counters are read at the end of an iteration
+    // and checked by each wave before its stores in the next one, so no
+    // barrier ever waits on memory and only a lagging neighbour costs a spin.
+    const int* flp = a.flags;  // lanes without a neighbour read the timeout word
+    int fkind = 0;             // 0: none, 1: same segment, 2: next segment
+    {
         const int nnz = 2 * a.rz + 1, n1 = (2 * a.ry + 1) * nnz;
-        int lane = tid, sg = seg, need = 0;
+        int lane = tid & 63, sg = seg;
+        fkind = 1;
         if (lane >= n1) {
-            if (!(has_next && r >= e - M)) return;
             lane -= n1;
-            if (lane >= n1) return;
             sg = nseg_next;
-            need = r - e + M + 1;
-        } else {
-            need = i - M + 1;
+            fkind = has_next ? 2 : 0;
         }
         int yy = ty + lane / nnz - a.ry, zz = tz + lane % nnz - a.rz;
+        if (lane >= n1) fkind = 0;
         if (g.wall[1]) {
-            if (yy < 0 || yy >= a.nty) return;
+            if (yy < 0 || yy >= a.nty) fkind = 0;
         } else {
             yy = wrapi(yy, a.nty);
         }
         if (g.wall[2]) {
-            if (zz < 0 || zz >= a.ntz) return;
+            if (zz < 0 || zz >= a.ntz) fkind = 0;
         } else {
             zz = wrapi(zz, a.ntz);
         }
-        const int* fl = a.flags + 1 + ((long long)sg * a.nty + yy) * a.ntz + zz;
+        if (fkind) flp = a.flags + 1 + ((long long)sg * a.nty + yy) * a.ntz + zz;
+    }
+    // plane r is stored in iteration i = r - s + 2M + 1; every work item whose
+    // halo covers it loads it in its iteration r - s' + M, i.e. has published
+    // a load front >= r - s' + M + 1
+    auto poll_need = [&](int i, int r) -> int {
+        if (fkind == 1) return i - M;
+        if (fkind == 2 && r >= e - M) return r - e + M + 1;
+        return -(1 << 30);
+    };
+    auto poll_issue = [&]() -> int { return __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    auto poll_finish = [&](int seen, int i, int r) {
+        const int need = poll_need(i, r);
+        if (__all(seen >= need)) return;
         // bounded wait: a timeout is recorded in flags[0] and the march goes on
-        for (int spin = 0; spin < (1 << 22); ++spin) {
-            if (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return;
+        bool ok = seen >= need;
+        for (int spin = 0; spin < (1 << 22) && !__all(ok); ++spin) {
             __builtin_amdgcn_s_sleep(2);
+            if (!ok) ok = __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
         }
-        __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!__all(ok) && (tid & 63) == 0) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
-    auto store = [&](const R (&out)[Q], int k, int r) {
-        T* base = f + (long long)r * PL + gofs[k];
+    // Stores, like loads, are issued every iteration by every slot; lanes that
+    // do not own a finished interior column carry an out-of-range offset and a
+    // plane that is not stored this iteration gets an empty range.
+    auto store = [&](const R (&out)[Q], int k, int r, bool live) {
+        const T* bq = f + (long long)(live ? r : 0) * PL;
+        const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) base[q * N] = Cd::enc(out[q]);
+        for (int q = 0; q < Q; ++q) {
+            Buf<T>::st(Cd::enc(out[q]), make_rsrc(bq, range), soff[k]);
+            bq += N;
+        }
     };
 
-    const int total = (e - s) + 2 * M;
-    issue_load(s - M);
+    // Pipeline of one iteration (load front at plane xl):
+    //   A  step-1 collide of plane xl on the tile plus M halo cells, then at
+    //      once the loads of plane xl+1 for the same column;
+    //   D  receive of the last step from the exchange filled one iteration
+    //      earlier: completes plane xl-M-1 (time t+M), stored in place after
+    //      the hazard check;
+    //   |  barrier, publish the load front;
+    //   E  (M = 2) receive of step 1 (completes plane xl-1 at t+1) and step-2
+    //      collide of that plane on the tile plus one halo cell;
+    //   |  (M = 2) barrier.
+    // Stores leave early and the loads of the next plane have the whole of E
+    // to arrive: the first wait of the next iteration finds them done.
+    R o1[K][3], o1p[K][3], o2[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o1[k][c] = o1p[k][c] = o2[k][c] = R(0);
+    const int total = (e - s) + 2 * M + 1;
+    issue_load(s - M, true);
+    int seen = poll_issue();
     for (int i = 0; i < total; ++i) {
         const int xl = s - M + i;
-        const int buf = (M == 1) ? (i & 1) : 0;
-        const int r_out = xl - M;
+        R* X1w = X1[(M == 1) ? (i & 1) : 0];        // filled by this iteration's step-1 collide
+        R* X1r = X1[(M == 1) ? ((i + 1) & 1) : 0];  // (M = 1) filled one iteration earlier
+        const int r_out = xl - M - 1;
         const bool storing = r_out >= s && r_out < e;
-        R* X1b = X1[buf];
+        const bool next_wanted = xl + 1 <= e - 1 + M;
 
-        // ---- step 1: collide plane xl on the tile plus M halo cells ----
-        R o1[K][3];
-        if (present(xl)) {
+        // ---- A: step-1 collide of plane xl, then the loads of plane xl+1 ----
+        R Fs[K][3];
+        const bool pres = present(xl);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if constexpr (FORCE) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
+            }
+            if (pres && rad[k] <= M && gofs[k] >= 0) {
+                R v[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
+                collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+                const int c = tid + k * NT;
+                sfor<0, Q>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + c] = v[q];
+                });
+                o1[k][0] = v[0];
+                o1[k][1] = v[1];
+                o1[k][2] = v[10];
+            }
+            issue_load_slot(xl + 1, next_wanted, k);
+        }
+
+        // ---- D: last-step receive, hazard check, in-place stores ----
+        if (storing) poll_finish(seen, i, r_out);
+        {
+            const int p = xl - M;  // plane collided by the last step one iteration ago
+            const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                o1[k][0] = o1[k][1] = o1[k][2] = R(0);
-                if (rad[k] <= M && gofs[k] >= 0) {
-                    R v[Q];
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
-                    collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+                const bool act = rad[k] == 0 && gofs[k] >= 0;
+                if constexpr (M == 2) {
+                    if (act) complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
+                    store(acc2[k], k, r_out, storing);
+                    if (act)
+                        deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
+                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+                } else {
                     const int c = tid + k * NT;
-                    sfor<0, Q>([&](auto qc) {
-                        constexpr int q = decltype(qc)::value;
-                        if constexpr (moves_yz(q)) X1b[yz_index(q) * NC + c] = v[q];
-                    });
-                    o1[k][0] = v[0];
-                    o1[k][1] = v[1];
-                    o1[k][2] = v[10];
+                    if (act) complete<R, WALLS>(acc1[k], X1r, NC, c, WZ, o1p[k][1], byz[k] | xbd);
+                    store(acc1[k], k, r_out, storing);
+                    if (act)
+                        deposit<R, WALLS>(acc1[k], nxt1[k], X1r, NC, c, WZ, o1p[k][0], o1p[k][1], o1p[k][2],
+                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
                 }
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; ++k) o1[k][0] = o1[k][1] = o1[k][2] = R(0);
         }
-        R Fs[K][3];
-        if constexpr (FORCE) {
+        if constexpr (M == 1) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
+                for (int c = 0; c < 3; ++c) o1p[k][c] = o1[k][c];
+            seen = poll_issue();
         }
-        if (i + 1 < total) issue_load(xl + 1);
-        if (M == 1 && storing) poll(i, r_out);
         __syncthreads();
         if (tid == 0) __hip_atomic_store(a.flags + 1 + wid, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-        // ---- receive step 1 on the tile plus M-1 halo cells: completes plane xl-1 ----
-        const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
-        R o2[K][3];
+        if constexpr (M == 2) {
+            // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
+            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
+            const bool coll2 = i >= M && present(xl - 1);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            o2[k][0] = o2[k][1] = o2[k][2] = R(0);
-            if (rad[k] <= M - 1 && gofs[k] >= 0) {
-                R out[Q];
-                receive<R, WALLS>(acc1[k], nxt1[k], out, X1b, NC, tid + k * NT, WZ, o1[k][0], o1[k][1], o1[k][2],
-                                  byz[k] | xbd1, byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
-                if constexpr (M == 1) {
-                    if (storing) store(out, k, r_out);
-                } else {
-                    // ---- step 2: collide plane xl-1 on the tile plus one halo cell ----
-                    if (i >= M && present(xl - 1)) {
-                        collide<R, FORCE>(out, omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+            for (int k = 0; k < K; ++k) {
+                if (rad[k] <= M - 1 && gofs[k] >= 0) {
+                    const int c = tid + k * NT;
+                    complete<R, WALLS>(acc1[k], X1w, NC, c, WZ, o1[k][1], byz[k] | xbd1);
+                    if (coll2) {
+                        collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
-                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = out[q];
+                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = acc1[k][q];
                         });
-                        o2[k][0] = out[0];
-                        o2[k][1] = out[1];
-                        o2[k][2] = out[10];
+                        o2[k][0] = acc1[k][0];
+                        o2[k][1] = acc1[k][1];
+                        o2[k][2] = acc1[k][10];
                     }
+                    deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, c, WZ, o1[k][0], o1[k][1], o1[k][2],
+                                      byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
                 }
-            }
-        }
-        if constexpr (M == 2) {
-            if constexpr (FORCE) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
+                if constexpr (FORCE) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) Fl2[k][c] = Fs[k][c];
-            }
-            if (storing) poll(i, r_out);
-            __syncthreads();
-            // ---- receive step 2 on the tile: completes plane xl-2, written in place ----
-            if (i >= M) {
-                const uint32_t xbd2 = xb(xl - 2), xbn2 = xb(xl - 1), xmn2 = xm(xl - 1);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (rad[k] == 0 && gofs[k] >= 0) {
-                        R out[Q];
-                        receive<R, WALLS>(acc2[k], nxt2[k], out, X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
-                                          byz[k] | xbd2, byz[k] | xbn2, myz[k] | xmn2, uwx, uwy, uwz);
-                        if (storing) store(out, k, r_out);
-                    }
                 }
             }
+            seen = poll_issue();
+            __syncthreads();
         }
     }
 }

@@ -4,12 +4,16 @@
 #pragma once
 
 #include "march.hpp"
+#include "march_pr.hpp"
 
 namespace lbm {
 
 template <int S, int M, int TY, int TZ, int NT, bool ALLOW_FORCE>
 struct Shape {
-    static bool match(const MarchPlan& p) { return p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT; }
+    static bool match(const MarchPlan& p)
+    {
+        return p.pr == 0 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+    }
     static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
     {
         if constexpr (ALLOW_FORCE) {
@@ -36,6 +40,40 @@ struct Shape {
     }
 };
 
+// A pair-and-ring shape (march_pr.hpp): NT = TY*TZ/2, needs an even nz.
+template <int S, int M, int TY, int TZ, bool ALLOW_FORCE>
+struct PRShape {
+    static constexpr int NT = TY * TZ / 2;
+    static bool match(const MarchPlan& p)
+    {
+        return p.pr == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+    }
+    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        if constexpr (ALLOW_FORCE) {
+            if (force)
+                return walls ? launch_march_pr_shape<S, M, TY, TZ, true, true>(p, a, s)
+                             : launch_march_pr_shape<S, M, TY, TZ, false, true>(p, a, s);
+        } else {
+            if (force) return hipErrorInvalidValue;
+        }
+        return walls ? launch_march_pr_shape<S, M, TY, TZ, true, false>(p, a, s)
+                     : launch_march_pr_shape<S, M, TY, TZ, false, false>(p, a, s);
+    }
+    static int max_blocks(bool walls, bool force)
+    {
+        if constexpr (ALLOW_FORCE) {
+            if (force)
+                return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, true>()
+                             : max_blocks_pr_shape<S, M, TY, TZ, false, true>();
+        } else {
+            if (force) return 0;
+        }
+        return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, false>()
+                     : max_blocks_pr_shape<S, M, TY, TZ, false, false>();
+    }
+};
+
 template <class... Shapes>
 struct ShapeList {
     static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
@@ -54,13 +92,16 @@ struct ShapeList {
     }
 };
 
-// Shapes per storage type, {M, TY, TZ, NT}, in variant order (variant v uses
-// entries 2v (M = 2) and 2v+1 (M = 1)).
+// Shapes per storage type, {M, TY, TZ, NT, pair_ring}, in variant order
+// (variant v uses entries 2v (M = 2) and 2v+1 (M = 1)).  Pair-and-ring
+// shapes need an even nz; the planner falls back to variant 1 otherwise.
 struct ShapeEntry {
-    int M, TY, TZ, NT;
+    int M, TY, TZ, NT, pr;
 };
-constexpr ShapeEntry kShapesF64[] = {{2, 12, 28, 512}, {1, 14, 30, 512}};
-constexpr ShapeEntry kShapesF32[] = {{2, 32, 32, 512}, {1, 32, 32, 512}};
+constexpr ShapeEntry kShapesF64[] = {{2, 12, 28, 512, 0}, {1, 14, 30, 512, 0}};
+constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1}, {1, 16, 64, 512, 1}, {2, 16, 64, 512, 0},
+                                     {1, 16, 64, 512, 0}, {2, 32, 32, 512, 1}, {1, 32, 32, 512, 1},
+                                     {2, 32, 32, 512, 0}, {1, 32, 32, 512, 0}};
 
 hipError_t launch_march_f64(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
 hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);

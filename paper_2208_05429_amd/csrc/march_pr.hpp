@@ -1,0 +1,466 @@
+// march_pr.hpp -- the marching in-place update of march.hpp laid out for
+// 32-bit arithmetic on CDNA4: every thread owns one pair of z-adjacent
+// interior columns of its tile and at most one column of the halo ring.
+//
+// Why this layout.  The interior of a TY x TZ tile is exactly TY*TZ/2 pairs, so
+// the interior loads and the in-place stores of a direction are 8-byte-per-
+// lane accesses that cover whole cache lines (a wave reads or writes two
+// rows of 64 floats), and a thread issues 19 pair loads + 19 ring loads + 19
+// pair stores per plane: fewer than the 63 vector-memory operations a wave
+// may have in flight, so no store ever waits for the prefetch.  Ring columns
+// (halo of width M) are never stored and never receive the last step, so
+// they carry no last-step pipeline registers.
+//
+// Pipeline of one iteration (load front at plane xl), as in march.hpp:
+//   A  step-1 collide of plane xl (pair and ring), each column's loads of
+//      plane xl+1 issued right after its collide;
+//   |  barrier, publish the load front;
+//   E  (M = 2) step-1 receive (completes plane xl-1 at t+1) and step-2
+//      collide of that plane on the tile plus one halo cell;  | barrier;
+//   D  receive of the last step: completes plane xl-M (time t+M) for the
+//      pair; each wave checks the neighbours' progress counters (read at the
+//      start of the iteration) and stores the pair in place.
+// The hazard protocol, the side planes of the segment ends and the boundary
+// rules are those of march.hpp.
+#pragma once
+
+#include "march.hpp"
+
+namespace lbm {
+
+// two z-adjacent values of one direction: one 8-byte (32-bit storage) or
+// 4-byte (16-bit storage) access
+template <class T>
+struct Buf2;
+template <>
+struct Buf2<float> {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float& a, float& b)
+    {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        a = __uint_as_float(v[0]);
+        b = __uint_as_float(v[1]);
+    }
+    static __device__ __forceinline__ void st(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        u2 w;
+        w[0] = __float_as_uint(a);
+        w[1] = __float_as_uint(b);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+    }
+};
+template <>
+struct Buf2<uint16_t> {
+    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t& a, uint16_t& b)
+    {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        a = uint16_t(v & 0xffffu);
+        b = uint16_t(v >> 16);
+    }
+    static __device__ __forceinline__ void st(uint16_t a, uint16_t b, __amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(uint32_t(a) | (uint32_t(b) << 16), r, off, 0, 0);
+    }
+};
+
+template <int M, int TY, int TZ>
+struct PairRingShape {
+    static constexpr int WY = TY + 2 * M, WZ = TZ + 2 * M, NC = WY * WZ;
+    static constexpr int NT = TY * TZ / 2;  // one interior pair per thread
+    static constexpr int RING = NC - TY * TZ;
+    static constexpr int WZ2 = TZ + 2, NC2 = (TY + 2) * WZ2;
+    static_assert(TZ % 2 == 0, "pairs need an even tile width");
+    static_assert(RING <= NT, "at most one ring column per thread");
+};
+
+// local (ly, lz) of ring cell r, row-major over the frame of the full tile
+template <int M, int TY, int TZ>
+__device__ __forceinline__ void ring_cell(int r, int& ly, int& lz)
+{
+    constexpr int WZ = TZ + 2 * M;
+    if (r < M * WZ) {
+        ly = r / WZ;
+        lz = r - ly * WZ;
+    } else if (r < M * WZ + TY * 2 * M) {
+        const int rr = r - M * WZ;
+        ly = M + rr / (2 * M);
+        const int k = rr - (rr / (2 * M)) * (2 * M);
+        lz = k < M ? k : TZ + k;
+    } else {
+        const int rr = r - M * WZ - TY * 2 * M;
+        ly = M + TY + rr / WZ;
+        lz = rr - (rr / WZ) * WZ;
+    }
+}
+
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
+{
+    using Cd = Codec<S>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    using Sh = PairRingShape<M, TY, TZ>;
+    constexpr int WZ = Sh::WZ, NC = Sh::NC, NT = Sh::NT, RING = Sh::RING, WZ2 = Sh::WZ2, NC2 = Sh::NC2;
+    constexpr int NB1 = (M == 1) ? 2 : 1;
+    constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
+    static_assert(M == 1 || M == 2, "one or two merged steps");
+    static_assert(sizeof(T) == 2 || sizeof(T) == 4, "32-bit arithmetic storages");
+
+    __shared__ R X1[NB1][16 * NC];
+    __shared__ R X2[(M == 2) ? 16 * NC2 : 1];
+
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+    int wid = blockIdx.x;
+    if (a.xcd_remap) {
+        const int per = gridDim.x >> 3;
+        wid = (wid & 7) * per + (wid >> 3);
+    }
+    const int tz = wid % a.ntz, ty = (wid / a.ntz) % a.nty, seg = wid / (a.ntz * a.nty);
+    const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
+    const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);
+    const bool wallx = g.wall[0] != 0;
+    const bool has_next = !wallx || seg + 1 < a.nseg;
+    const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
+    const R omega = R(g.omega);
+    const R uwx = R(g.uw[0]), uwy = R(g.uw[1]), uwz = R(g.uw[2]);
+    const long long N = g.N, PL = g.PL;
+
+    // ---- the three columns of this thread: 0, 1 = interior pair, 2 = ring ----
+    constexpr int K = 3;
+    int gofs[K], rad[K], ci[K], ci2[K];
+    uint32_t voff[K], byz[K], myz[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gofs[k] = -1;
+        rad[k] = M + 1;
+        ci[k] = 0;
+        ci2[k] = 0;
+        voff[k] = kOffNone;
+        byz[k] = 0;
+        myz[k] = 0;
+        int ly = 0, lz = 0;
+        bool have = true;
+        if (k < 2) {
+            ly = M + tid / (TZ / 2);
+            lz = M + 2 * (tid - (tid / (TZ / 2)) * (TZ / 2)) + k;
+        } else if (tid < RING) {
+            ring_cell<M, TY, TZ>(tid, ly, lz);
+        } else {
+            have = false;
+        }
+        if (!have) continue;
+        ci[k] = ly * WZ + lz;
+        if (ly >= TYe + 2 * M || lz >= TZe + 2 * M) continue;
+        const int dy = ly < M ? M - ly : (ly >= M + TYe ? ly - (M + TYe) + 1 : 0);
+        const int dz = lz < M ? M - lz : (lz >= M + TZe ? lz - (M + TZe) + 1 : 0);
+        int y = ty * TY - M + ly, z = tz * TZ - M + lz;
+        bool inside = true;
+        if (g.wall[1]) inside = inside && y >= 0 && y < g.ny;
+        else y = wrapi(y, g.ny);
+        if (g.wall[2]) inside = inside && z >= 0 && z < g.nz;
+        else z = wrapi(z, g.nz);
+        if (!inside) continue;
+        gofs[k] = y * g.nz + z;
+        voff[k] = uint32_t(gofs[k]) * uint32_t(sizeof(T));
+        rad[k] = dy > dz ? dy : dz;
+        ci2[k] = (ly - 1) * WZ2 + (lz - 1);
+        if constexpr (WALLS) {
+            uint32_t b = 0, mv = 0;
+            sfor<1, Q>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if constexpr (moves_yz(q)) {
+                    const int ys = y - cyq(q), zs = z - czq(q);
+                    int f1 = -1, f2 = -1;
+                    if (g.wall[1] && ys < 0) f1 = 2;
+                    if (g.wall[1] && ys >= g.ny) f1 = 3;
+                    if (g.wall[2] && zs < 0) f2 = 4;
+                    if (g.wall[2] && zs >= g.nz) f2 = 5;
+                    if (f1 >= 0 || f2 >= 0) b |= 1u << q;
+                    if (g.moving_face >= 0 && (f1 == g.moving_face || f2 == g.moving_face)) mv |= 1u << q;
+                }
+            });
+            byz[k] = b;
+            myz[k] = mv;
+        }
+    }
+    // memory offsets: the pair moves as one access keyed on its first column
+    // (a pair starts at an even z of an even-length row, so it never wraps)
+    const bool pair_loads = rad[0] <= M && gofs[0] >= 0;
+    const uint32_t loffP = pair_loads ? voff[0] : kOffNone;
+    const uint32_t soffP = (rad[0] == 0 && gofs[0] >= 0) ? voff[0] : kOffNone;
+    const uint32_t loffG = (rad[2] <= M && gofs[2] >= 0) ? voff[2] : kOffNone;
+    const uint32_t loffPR = pair_loads ? uint32_t(gofs[0]) * uint32_t(sizeof(R)) : kOffNone;
+    const uint32_t loffGR = (rad[2] <= M && gofs[2] >= 0) ? uint32_t(gofs[2]) * uint32_t(sizeof(R)) : kOffNone;
+
+    auto xb = [&](int p) -> uint32_t {
+        if (!wallx) return 0u;
+        return (p == 0 ? CXP : 0u) | (p == g.nx - 1 ? CXM : 0u);
+    };
+    auto xm = [&](int p) -> uint32_t {
+        if (!wallx) return 0u;
+        return ((p == 0 && g.moving_face == 0) ? CXP : 0u) | ((p == g.nx - 1 && g.moving_face == 1) ? CXM : 0u);
+    };
+    auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
+
+    // ---- pipeline registers ----
+    T Lr[K][Q];
+    R Fl1[K][3], Fl2[K][3];
+    R acc1[K][Q], nxt1[K][5];  // step 1: pair and ring
+    R acc2[2][Q], nxt2[2][5];  // last step of M = 2: pair only
+    R o1[K][3], o2[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Lr[k][q] = T(0);
+            acc1[k][q] = R(0);
+            if (k < 2) acc2[k][q] = R(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            nxt1[k][j] = R(0);
+            if (k < 2) nxt2[k][j] = R(0);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Fl1[k][c] = Fl2[k][c] = o1[k][c] = o2[k][c] = R(0);
+    }
+
+    T* __restrict__ f = static_cast<T*>(a.f);
+    const T* __restrict__ side = static_cast<const T*>(a.side);
+    const R* __restrict__ F = static_cast<const R*>(a.force);
+    const uint32_t plane_bytes = uint32_t(PL) * uint32_t(sizeof(T));
+
+    // Loads are issued every iteration, unconditionally (empty range when the
+    // plane is absent or past the end), so the outstanding-operation counts
+    // the compiler tracks stay exact.
+    auto plane_base = [&](int xp, long long& qstride) -> const T* {
+        if (xp >= e && has_next) {
+            qstride = PL;
+            return side + ((long long)(nseg_next * M + (xp - e)) * Q) * PL;
+        }
+        qstride = N;
+        return f + (long long)wrapi(xp, g.nx) * PL;
+    };
+    auto load_force = [&](int xp, bool live, int k, uint32_t off) {
+        if constexpr (FORCE) {
+            const uint32_t rangeR = live ? uint32_t(PL) * uint32_t(sizeof(R)) : 0u;
+            const R* bc = F + (long long)wrapi(xp, g.nx) * PL;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Fl1[k][c] = Buf<R>::ld(make_rsrc(bc, rangeR), off);
+                bc += N;
+            }
+        }
+    };
+    auto load_pair = [&](int xp, bool wanted) {
+        const bool live = wanted && present(xp);
+        long long qs;
+        const T* bq = plane_base(xp, qs);
+        const uint32_t range = live ? plane_bytes : 0u;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Buf2<T>::ld(make_rsrc(bq, range), loffP, Lr[0][q], Lr[1][q]);
+            bq += qs;
+        }
+        if constexpr (FORCE) {
+            load_force(xp, live, 0, loffPR);
+            const uint32_t off1 = loffPR == kOffNone ? kOffNone : loffPR + uint32_t(sizeof(R));
+            load_force(xp, live, 1, off1);
+        }
+    };
+    auto load_ring = [&](int xp, bool wanted) {
+        const bool live = wanted && present(xp);
+        long long qs;
+        const T* bq = plane_base(xp, qs);
+        const uint32_t range = live ? plane_bytes : 0u;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Lr[2][q] = Buf<T>::ld(make_rsrc(bq, range), loffG);
+            bq += qs;
+        }
+        load_force(xp, live, 2, loffGR);
+    };
+
+    // hazard check (see march.hpp): every wave reads the counters of the
+    // neighbouring work items at the start of an iteration and checks them
+    // before its stores at the end of it
+    const int* flp = a.flags;
+    int fkind = 0;
+    {
+        const int nnz = 2 * a.rz + 1, n1 = (2 * a.ry + 1) * nnz;
+        int lane = tid & 63, sg = seg;
+        fkind = 1;
+        if (lane >= n1) {
+            lane -= n1;
+            sg = nseg_next;
+            fkind = has_next ? 2 : 0;
+        }
+        int yy = ty + lane / nnz - a.ry, zz = tz + lane % nnz - a.rz;
+        if (lane >= n1) fkind = 0;
+        if (g.wall[1]) {
+            if (yy < 0 || yy >= a.nty) fkind = 0;
+        } else {
+            yy = wrapi(yy, a.nty);
+        }
+        if (g.wall[2]) {
+            if (zz < 0 || zz >= a.ntz) fkind = 0;
+        } else {
+            zz = wrapi(zz, a.ntz);
+        }
+        if (fkind) flp = a.flags + 1 + ((long long)sg * a.nty + yy) * a.ntz + zz;
+    }
+    // plane r is stored in iteration i = r - s + 2M; a work item whose halo
+    // covers it loads it in its iteration r - s' + M
+    auto poll_need = [&](int i, int r) -> int {
+        if (fkind == 1) return i - M + 1;
+        if (fkind == 2 && r >= e - M) return r - e + M + 1;
+        return -(1 << 30);
+    };
+    auto poll_finish = [&](int seen, int i, int r) {
+        const int need = poll_need(i, r);
+        if (__all(seen >= need)) return;
+        bool ok = seen >= need;
+        for (int spin = 0; spin < (1 << 22) && !__all(ok); ++spin) {
+            __builtin_amdgcn_s_sleep(2);
+            if (!ok) ok = __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+        }
+        if (!__all(ok) && (tid & 63) == 0) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+
+    auto store_pair = [&](const R (&v0)[Q], const R (&v1)[Q], int r, bool live) {
+        const T* bq = f + (long long)(live ? r : 0) * PL;
+        const uint32_t range = live ? plane_bytes : 0u;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Buf2<T>::st(Cd::enc(v0[q]), Cd::enc(v1[q]), make_rsrc(bq, range), soffP);
+            bq += N;
+        }
+    };
+
+    auto collide1 = [&](int k, R* X1w) {
+        R v[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
+        collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+        sfor<0, Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + ci[k]] = v[q];
+        });
+        o1[k][0] = v[0];
+        o1[k][1] = v[1];
+        o1[k][2] = v[10];
+    };
+
+    const int total = (e - s) + 2 * M;
+    load_pair(s - M, true);
+    load_ring(s - M, true);
+    for (int i = 0; i < total; ++i) {
+        const int xl = s - M + i;
+        R* X1w = X1[(M == 1) ? (i & 1) : 0];
+        const int r_out = xl - M;
+        const bool storing = r_out >= s && r_out < e;
+        const bool next_wanted = i + 1 < total;
+        const int seen = __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+        // ---- A: step-1 collide of plane xl; loads of plane xl+1 follow each column ----
+        R Fs[K][3];
+        if constexpr (FORCE) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
+        }
+        const bool pres = present(xl);
+        if (pres && rad[0] <= M && gofs[0] >= 0) collide1(0, X1w);
+        if (pres && rad[1] <= M && gofs[1] >= 0) collide1(1, X1w);
+        load_pair(xl + 1, next_wanted);
+        if (pres && rad[2] <= M && gofs[2] >= 0) collide1(2, X1w);
+        load_ring(xl + 1, next_wanted);
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(a.flags + 1 + wid, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+        if constexpr (M == 2) {
+            // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
+            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
+            const bool coll2 = i >= M && present(xl - 1);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (rad[k] <= 1 && gofs[k] >= 0) {
+                    complete<R, WALLS>(acc1[k], X1w, NC, ci[k], WZ, o1[k][1], byz[k] | xbd1);
+                    if (coll2) {
+                        collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        sfor<0, Q>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = acc1[k][q];
+                        });
+                        o2[k][0] = acc1[k][0];
+                        o2[k][1] = acc1[k][1];
+                        o2[k][2] = acc1[k][10];
+                    }
+                    deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, ci[k], WZ, o1[k][0], o1[k][1], o1[k][2],
+                                      byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
+                }
+                if constexpr (FORCE) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Fl2[k][c] = Fs[k][c];
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- D: last-step receive of the pair, hazard check, in-place store ----
+        {
+            const int p = xl - M + 1;  // plane the last step collided
+            const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
+            const bool act = rad[0] == 0 && gofs[0] >= 0;
+            if constexpr (M == 2) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (act) complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
+                if (storing) poll_finish(seen, i, r_out);
+                store_pair(acc2[0], acc2[1], r_out, storing);
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (act)
+                        deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
+                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (act) complete<R, WALLS>(acc1[k], X1w, NC, ci[k], WZ, o1[k][1], byz[k] | xbd);
+                if (storing) poll_finish(seen, i, r_out);
+                store_pair(acc1[0], acc1[1], r_out, storing);
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (act)
+                        deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, ci[k], WZ, o1[k][0], o1[k][1], o1[k][2],
+                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+            }
+        }
+    }
+}
+
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE>
+hipError_t launch_march_pr_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
+{
+    auto kern = k_march_pr<S, M, TY, TZ, WALLS, FORCE>;
+    MarchArgs arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks),
+                                      dim3(PairRingShape<M, TY, TZ>::NT), params, 0, st);
+}
+
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE>
+int max_blocks_pr_shape()
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_pr<S, M, TY, TZ, WALLS, FORCE>,
+                                                     PairRingShape<M, TY, TZ>::NT, 0) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+}  // namespace lbm

@@ -94,12 +94,16 @@ def test_tgv32_16bit_storage_error_is_bounded(tgv32_ref, storage, bound):
 # --------------------------------------------------------------------------
 
 CASES = [
-    # shape, faces, wall_u
+    # shape, faces, wall_u  (odd nz runs the plain-slot kernels, even nz the pair-and-ring ones)
     ((20, 37, 45), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, -0.02)),
     ((23, 30, 61), (PERIODIC, PERIODIC, WALL, WALL, MOVING_WALL, WALL), (0.03, -0.02, 0.0)),
     ((17, 41, 33), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
     ((26, 13, 70), (MOVING_WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.04, 0.01)),
+    ((20, 37, 68), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, -0.02)),
+    ((19, 35, 130), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((21, 18, 66), (PERIODIC, PERIODIC, WALL, WALL, MOVING_WALL, WALL), (0.03, -0.02, 0.0)),
 ]
+VARIANTS = [0, 1, 2, 3]  # 32-bit storages: 16x64 pair-ring, 16x64 slots, 32x32 pair-ring, 32x32 slots
 
 
 def _noisy_init(shape, seed):
@@ -128,15 +132,31 @@ def test_ragged_fp32_schemes_agree(case):
     o = Oracle(shape, 0.6, faces=faces, wall_u=wall_u)
     steps = 7
     ref = o.run(o.init(rho0, u0), steps)
-    states = {}
-    for scheme in SCHEMES:
-        lat, _, _, _ = gpu_run(shape, 0.6, "f32", scheme, faces, wall_u, rho0, u0, steps=steps)
-        states[scheme] = lat.f.cpu().numpy()
-        assert rel(lat.distributions(), ref) <= 2e-6, scheme
-    # the three schemes run the same per-cell arithmetic: any difference is a race or an indexing slip
-    a = states["two_array"]
+    lat, _, _, _ = gpu_run(shape, 0.6, "f32", "two_array", faces, wall_u, rho0, u0, steps=steps)
+    a = lat.f.cpu().numpy()
+    assert rel(lat.distributions(), ref) <= 2e-6
+    # every in-place kernel shape runs the same per-cell arithmetic as the plain
+    # scheme: any difference is a race or an indexing slip
+    for variant in VARIANTS:
+        for scheme in ("swap1", "swap2"):
+            lat, _, _, _ = gpu_run(shape, 0.6, "f32", scheme, faces, wall_u, rho0, u0, steps=steps, variant=variant)
+            assert np.array_equal(lat.f.cpu().numpy().view(np.uint32), a.view(np.uint32)), (scheme, variant)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("case", [0, 4, 5])
+def test_ragged_16bit_kernel_shapes_agree(storage, case):
+    # 16-bit storage rounds every stored value, so shapes agree bitwise only if
+    # each runs the same per-cell arithmetic on the same inputs
+    shape, faces, wall_u = CASES[case]
+    rho0, u0 = _noisy_init(shape, 250 + case)
     for scheme in ("swap1", "swap2"):
-        assert np.array_equal(states[scheme].view(np.uint32), a.view(np.uint32)), scheme
+        states = []
+        for variant in VARIANTS:
+            lat, _, _, _ = gpu_run(shape, 0.6, storage, scheme, faces, wall_u, rho0, u0, steps=5, variant=variant)
+            states.append(lat.f.view(torch.int16).cpu().numpy().copy())
+        for v, st in zip(VARIANTS[1:], states[1:]):
+            assert np.array_equal(st, states[0]), (scheme, v)
 
 
 def test_force_channel_fp64_and_fp32():

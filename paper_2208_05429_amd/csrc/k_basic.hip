@@ -85,11 +85,11 @@ __global__ __launch_bounds__(256) void k_two_array(Geom g, const typename Codec<
 // ------------------------------------------------------------------------
 // Prepass of a marching pass: save the time-t copies of the first M planes of
 // every segment and clear the progress counters (flags[0] is the timeout
-// word, flags[1..] one counter per work item).
+// word, flags[(1 + w) * fstride] the counter of work item w).
 // ------------------------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(256) void k_prepass(Geom g, const T* __restrict__ f, T* __restrict__ side, int* flags,
-                                                 int nflags, int M, int seg_len, int nseg)
+                                                 int nflags, int fstride, int M, int seg_len, int nseg)
 {
     const long long per = (long long)Q * g.PL;
     const long long total = (long long)nseg * M * per;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_prepass(Geom g, const T* __restrict__ f
         side[t] = f[q * g.N + (long long)plane * g.PL + o];
     }
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < nflags; t += (long long)gridDim.x * 256)
-        flags[t] = 0;
+        flags[t * fstride] = 0;
 }
 
 // ------------------------------------------------------------------------
@@ -248,7 +248,7 @@ static hipError_t prepass_t(const Geom& g, const MarchPlan& p, const void* f, vo
     if (blocks < 1) blocks = 1;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_prepass<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
-                       static_cast<T*>(side), flags, p.blocks + 1, p.M, p.seg_len, p.nseg);
+                       static_cast<T*>(side), flags, p.blocks + 1, p.flag_stride, p.M, p.seg_len, p.nseg);
     return hipGetLastError();
 }
 

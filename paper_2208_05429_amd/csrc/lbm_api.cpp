@@ -41,6 +41,10 @@ namespace {
 thread_local std::string g_create_err;
 constexpr int kMaxResident = 256;  // MI355X: 256 CUs, one marching workgroup per CU
 constexpr size_t kAlign = 256;
+// Progress counters are polled by every wave of every workgroup each plane;
+// packed into a few cache lines they become a memory hot spot, so each gets
+// its own stretch of memory.
+constexpr int kFlagStride = 1024;  // ints (4 KB)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t elem_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
@@ -104,7 +108,8 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     r.blocks = tiles * nseg;
     r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
     r.side_bytes = size_t(nseg) * size_t(M) * 19u * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
-    r.flag_bytes = size_t(r.blocks + 1) * sizeof(int);
+    r.flag_stride = kFlagStride;
+    r.flag_bytes = size_t(r.blocks + 1) * size_t(kFlagStride) * sizeof(int);
     *p = r;
     return LBM_OK;
 }
@@ -309,6 +314,7 @@ lbm_status march_pass(lbm_ctx* ctx, int M)
     a.ry = p.ry;
     a.rz = p.rz;
     a.xcd_remap = p.xcd_remap;
+    a.fstride = p.flag_stride;
     const bool walls = ctx->g.wall[0] || ctx->g.wall[1] || ctx->g.wall[2];
     const bool force = ctx->force != nullptr;
     hipError_t e;

@@ -30,7 +30,8 @@ struct MarchPlan {
     int blocks = 0;              // nty*ntz*nseg work items, all co-resident
     int xcd_remap = 0;           // map consecutive work items onto one XCD
     size_t side_bytes = 0;       // side planes: nseg * M planes * 19 values
-    size_t flag_bytes = 0;       // one int per work item
+    int flag_stride = 1;         // ints between two progress counters
+    size_t flag_bytes = 0;       // timeout word + one counter per work item
 };
 
 struct MarchArgs {
@@ -40,6 +41,7 @@ struct MarchArgs {
     const void* force;  // 3N or null
     int* flags;         // progress (planes loaded) of every work item
     int nty, ntz, nseg, seg_len, ry, rz, xcd_remap;
+    int fstride;  // ints between two progress counters (counter of work item w at flags[(1 + w) * fstride])
 };
 
 // Launchers; each returns the hipError_t of its launch.

@@ -338,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         } else {
             zz = wrapi(zz, a.ntz);
         }
-        if (fkind) flp = a.flags + 1 + ((long long)sg * a.nty + yy) * a.ntz + zz;
+        if (fkind) flp = a.flags + (1 + ((long long)sg * a.nty + yy) * a.ntz + zz) * a.fstride;
     }
     // plane r is stored in iteration i = r - s + 2M + 1; every work item whose
     // halo covers it loads it in its iteration r - s' + M, i.e. has published
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             seen = poll_issue();
         }
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.flags + 1 + wid, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.flags + (1 + (long long)wid) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----

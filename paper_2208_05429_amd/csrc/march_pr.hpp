@@ -63,6 +63,87 @@ struct Buf2<uint16_t> {
     }
 };
 
+// Exchange buffers are split by column parity: column c of a row-major grid
+// with an even row length lives at (c & 1) * (size / 2) + (c >> 1), so the
+// lanes of a wave, which own consecutive pairs, touch consecutive words
+// (a plain row-major buffer would give stride-2 bank conflicts).  PAR is the
+// parity of the column when known at compile time (pair columns), -1 else.
+template <int PAR, int HALF>
+__device__ __forceinline__ int split_at(int c, int d)
+{
+    if constexpr (PAR >= 0) {
+        const int t = PAR + d;  // d is a compile-time constant at every call site
+        return ((t & 1) ? HALF : 0) + (c >> 1) + (t >> 1);
+    } else {
+        const int cc = c + d;
+        return ((cc & 1) ? HALF : 0) + (cc >> 1);
+    }
+}
+
+// complete() / deposit() of march.hpp on a parity-split buffer of 16 rows of
+// STRIDE columns with row pitch WZL.
+template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
+__device__ __forceinline__ void complete_s(R (&acc)[Q], const R* __restrict__ X, int ci, R o1, uint32_t bdone)
+{
+    constexpr int HALF = STRIDE / 2;
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (cxq(q) == -1) {
+            R rv;
+            if constexpr (moves_yz(q))
+                rv = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
+            else
+                rv = o1;
+            if constexpr (WALLS)
+                acc[q] = ((bdone >> q) & 1u) ? acc[q] : rv;
+            else
+                acc[q] = rv;
+        }
+    });
+}
+
+template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
+__device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], const R* __restrict__ X, int ci, R o0, R o1,
+                                          R o10, uint32_t bnext, uint32_t mnext, R uwx, R uwy, R uwz)
+{
+    constexpr int HALF = STRIDE / 2;
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int qo = oppq(q);
+        R bval = R(0);
+        if constexpr (WALLS && q != 0) {
+            if constexpr (moves_yz(qo))
+                bval = X[yz_index(qo) * STRIDE + split_at<PAR, HALF>(ci, 0)];
+            else
+                bval = (qo == 1) ? o1 : o10;
+            if ((mnext >> q) & 1u) bval += wall_term<q>(uwx, uwy, uwz);
+        }
+        if constexpr (cxq(q) == 0) {
+            R rv;
+            if constexpr (q == 0)
+                rv = o0;
+            else
+                rv = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
+            if constexpr (WALLS && q != 0)
+                acc[q] = ((bnext >> q) & 1u) ? bval : rv;
+            else
+                acc[q] = rv;
+        } else if constexpr (cxq(q) == 1) {
+            constexpr int j = xp_index(q);
+            if constexpr (WALLS)
+                acc[q] = ((bnext >> q) & 1u) ? bval : nxt[j];
+            else
+                acc[q] = nxt[j];
+            if constexpr (moves_yz(q))
+                nxt[j] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
+            else
+                nxt[j] = o10;
+        } else {
+            if constexpr (WALLS) acc[q] = bval;
+        }
+    });
+}
+
 template <int M, int TY, int TZ>
 struct PairRingShape {
     static constexpr int WY = TY + 2 * M, WZ = TZ + 2 * M, NC = WY * WZ;
@@ -308,7 +389,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         } else {
             zz = wrapi(zz, a.ntz);
         }
-        if (fkind) flp = a.flags + 1 + ((long long)sg * a.nty + yy) * a.ntz + zz;
+        if (fkind) flp = a.flags + (1 + ((long long)sg * a.nty + yy) * a.ntz + zz) * a.fstride;
     }
     // plane r is stored in iteration i = r - s + 2M; a work item whose halo
     // covers it loads it in its iteration r - s' + M
@@ -343,9 +424,10 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 #pragma unroll
         for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
         collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+        const int sl = ((ci[k] & 1) ? NC / 2 : 0) + (ci[k] >> 1);
         sfor<0, Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + ci[k]] = v[q];
+            if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + sl] = v[q];
         });
         o1[k][0] = v[0];
         o1[k][1] = v[1];
@@ -378,34 +460,37 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         if (pres && rad[2] <= M && gofs[2] >= 0) collide1(2, X1w);
         load_ring(xl + 1, next_wanted);
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.flags + 1 + wid, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.flags + (1 + (long long)wid) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
             const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
             const bool coll2 = i >= M && present(xl - 1);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
+            sfor<0, K>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int PAR = (k == 0) ? (M & 1) : ((k == 1) ? ((M + 1) & 1) : -1);  // parity of ci
+                constexpr int PAR2 = (k == 0) ? 1 : ((k == 1) ? 0 : -1);                 // parity of ci2
                 if (rad[k] <= 1 && gofs[k] >= 0) {
-                    complete<R, WALLS>(acc1[k], X1w, NC, ci[k], WZ, o1[k][1], byz[k] | xbd1);
+                    complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], byz[k] | xbd1);
                     if (coll2) {
                         collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        const int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
-                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = acc1[k][q];
+                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + sl2] = acc1[k][q];
                         });
                         o2[k][0] = acc1[k][0];
                         o2[k][1] = acc1[k][1];
                         o2[k][2] = acc1[k][10];
                     }
-                    deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, ci[k], WZ, o1[k][0], o1[k][1], o1[k][2],
-                                      byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
+                    deposit_s<R, WALLS, PAR, NC, WZ>(acc1[k], nxt1[k], X1w, ci[k], o1[k][0], o1[k][1], o1[k][2],
+                                                     byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
                 }
                 if constexpr (FORCE) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) Fl2[k][c] = Fs[k][c];
                 }
-            }
+            });
             __syncthreads();
         }
 
@@ -415,27 +500,31 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
             const bool act = rad[0] == 0 && gofs[0] >= 0;
             if constexpr (M == 2) {
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (act) complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
+                if (act) {
+                    complete_s<R, WALLS, 1, NC2, WZ2>(acc2[0], X2, ci2[0], o2[0][1], byz[0] | xbd);
+                    complete_s<R, WALLS, 0, NC2, WZ2>(acc2[1], X2, ci2[1], o2[1][1], byz[1] | xbd);
+                }
                 if (storing) poll_finish(seen, i, r_out);
                 store_pair(acc2[0], acc2[1], r_out, storing);
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (act)
-                        deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
-                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+                if (act) {
+                    deposit_s<R, WALLS, 1, NC2, WZ2>(acc2[0], nxt2[0], X2, ci2[0], o2[0][0], o2[0][1], o2[0][2],
+                                                     byz[0] | xbn, myz[0] | xmn, uwx, uwy, uwz);
+                    deposit_s<R, WALLS, 0, NC2, WZ2>(acc2[1], nxt2[1], X2, ci2[1], o2[1][0], o2[1][1], o2[1][2],
+                                                     byz[1] | xbn, myz[1] | xmn, uwx, uwy, uwz);
+                }
             } else {
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (act) complete<R, WALLS>(acc1[k], X1w, NC, ci[k], WZ, o1[k][1], byz[k] | xbd);
+                if (act) {
+                    complete_s<R, WALLS, 1, NC, WZ>(acc1[0], X1w, ci[0], o1[0][1], byz[0] | xbd);
+                    complete_s<R, WALLS, 0, NC, WZ>(acc1[1], X1w, ci[1], o1[1][1], byz[1] | xbd);
+                }
                 if (storing) poll_finish(seen, i, r_out);
                 store_pair(acc1[0], acc1[1], r_out, storing);
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (act)
-                        deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, ci[k], WZ, o1[k][0], o1[k][1], o1[k][2],
-                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+                if (act) {
+                    deposit_s<R, WALLS, 1, NC, WZ>(acc1[0], nxt1[0], X1w, ci[0], o1[0][0], o1[0][1], o1[0][2],
+                                                   byz[0] | xbn, myz[0] | xmn, uwx, uwy, uwz);
+                    deposit_s<R, WALLS, 0, NC, WZ>(acc1[1], nxt1[1], X1w, ci[1], o1[1][0], o1[1][1], o1[1][2],
+                                                   byz[1] | xbn, myz[1] | xmn, uwx, uwy, uwz);
+                }
             }
         }
     }

@@ -1,0 +1,85 @@
+"""Gradients of a loss of the final velocity field with respect to a per-cell
+body force, through the library's discrete adjoint (argument marshalling only).
+
+Forward: T time steps from f0 under the Guo force F, keeping the state every
+`checkpoint` steps.  Backward: lambda_T = dL/df_T from dL/du (lbm_macro_adjoint,
+which also adds the direct dL/dF), then for each checkpoint segment in
+reverse: restore the checkpoint, recompute the segment's states, and run the
+adjoint of each step backwards (lbm_step_adjoint), accumulating dL/dF.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import capi
+from .lattice import Lattice, real_dtype
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class ForceAdjoint(torch.autograd.Function):
+    """u_T = ForceAdjoint.apply(F, f0, spec); spec = dict(shape, tau, storage,
+    faces, wall_u, steps, checkpoint[, merged])."""
+
+    @staticmethod
+    def forward(ctx, F, f0, spec):
+        shape, storage = tuple(spec["shape"]), spec["storage"]
+        steps, k = int(spec["steps"]), int(spec["checkpoint"])
+        lat = Lattice(shape, spec["tau"], storage, spec.get("scheme", "swap2"), spec["faces"],
+                      spec.get("wall_u", (0.0, 0.0, 0.0)), force=F.detach(), f=f0.detach().clone())
+        ckpts = []
+        t = 0
+        while t < steps:
+            ckpts.append(lat.f.clone())
+            n = min(k, steps - t)
+            lat.step(n)
+            t += n
+        _, u, _, _ = lat.macroscopic(want=("u",))
+        ctx.lat, ctx.ckpts, ctx.spec = lat, ckpts, spec
+        ctx.save_for_backward(F)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        lat, ckpts, spec = ctx.lat, ctx.ckpts, ctx.spec
+        steps, k = int(spec["steps"]), int(spec["checkpoint"])
+        merged = bool(spec.get("merged", False))
+        shape = lat.shape
+        rdt = real_dtype(lat.storage)
+        dev = lat.device
+        lam = torch.empty((19,) + shape, dtype=rdt, device=dev)
+        lam2 = torch.empty_like(lam)
+        gF = torch.zeros((3,) + shape, dtype=rdt, device=dev)
+        gu = grad_u.to(device=dev, dtype=rdt).contiguous()
+        capi.lbm_set_stream(lat.ctx, torch.cuda.current_stream().cuda_stream)
+        capi.lbm_macro_adjoint(lat.ctx, _ptr(lat.f), _ptr(gu), _ptr(lam), _ptr(gF))
+        for seg in range(len(ckpts) - 1, -1, -1):
+            t0 = seg * k
+            n = min(k, steps - t0)
+            lat.f.copy_(ckpts[seg])
+            states = [ckpts[seg]]
+            for _ in range(n - 1):
+                lat.step(1)
+                states.append(lat.f.clone())
+            t = n
+            while t > 0:
+                if merged and t >= 2:
+                    capi.lbm_step_adjoint(lat.ctx, _ptr(states[t - 2]), _ptr(lam), _ptr(lam2), _ptr(gF), 2)
+                    t -= 2
+                else:
+                    capi.lbm_step_adjoint(lat.ctx, _ptr(states[t - 1]), _ptr(lam), _ptr(lam2), _ptr(gF), 1)
+                    t -= 1
+                lam, lam2 = lam2, lam
+        F, = ctx.saved_tensors
+        return gF.to(F.dtype), None, None
+
+
+def force_gradient(F, f0, spec, u_target):
+    """(L, dL/dF) for L = sum (u_T - u*)^2, through ForceAdjoint."""
+    Fp = F.detach().clone().requires_grad_(True)
+    u = ForceAdjoint.apply(Fp, f0, spec)
+    L = ((u - u_target) ** 2).sum()
+    L.backward()
+    return float(L.detach()), Fp.grad

@@ -1,0 +1,117 @@
+"""GPU discrete adjoint (through the C ABI) against the FP64 oracle's adjoint,
+and the whole-run force gradient against central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import PERIODIC, WALL, Oracle
+from paper_2208_05429_amd import workloads as wl
+from paper_2208_05429_amd import capi
+from paper_2208_05429_amd.adjoint import force_gradient
+from paper_2208_05429_amd.lattice import Lattice, real_dtype
+
+pytestmark = pytest.mark.gpu
+
+FACES = (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL)
+NAMES = ("periodic", "periodic", "wall", "wall", "wall", "wall")
+
+
+def _init(shape, seed):
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    return wl.random_density(shape, 0.01, seed), u0 + wl.uniform_noise(shape, 5e-3, seed + 1)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_adjoint_seed_and_one_step_match_oracle(storage, tol):
+    shape = (10, 13, 12)
+    rho0, u0 = _init(shape, 5)
+    F = wl.normal_field(shape, 1e-4, 6)
+    o = Oracle(shape, 0.8, faces=FACES)
+    f_t = o.run(o.init(rho0, u0), 3, F)
+    lam_next = wl.normal_field(shape, 1.0, 7, comps=19)
+    ut = wl.normal_field(shape, 1e-2, 8)
+    seed_ref, gseed_ref = o.loss_seed(f_t, ut, F)
+    lam_ref, g_ref = o.adjoint_step(f_t, lam_next, F)
+
+    rdt = real_dtype(storage)
+    lat = Lattice(shape, 0.8, storage, "swap2", NAMES, force=torch.as_tensor(F),
+                  rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0))
+    lat.step(3)
+    _, u, _, _ = lat.macroscopic(want=("u",))
+    gu = (2 * (u - torch.as_tensor(ut, device=u.device))).to(rdt).contiguous()
+    lam = torch.empty((19,) + shape, dtype=rdt, device="cuda")
+    gF = torch.zeros((3,) + shape, dtype=rdt, device="cuda")
+    capi.lbm_macro_adjoint(lat.ctx, lat.f.data_ptr(), gu.data_ptr(), lam.data_ptr(), gF.data_ptr())
+    torch.cuda.synchronize()
+    e = np.abs(lam.double().cpu().numpy() - seed_ref).max() / np.abs(seed_ref).max()
+    assert e <= 10 * tol, e
+    assert np.abs(gF.double().cpu().numpy() - gseed_ref).max() <= 10 * tol * np.abs(gseed_ref).max()
+
+    lin = torch.as_tensor(lam_next, dtype=rdt, device="cuda").contiguous()
+    lout = torch.empty_like(lin)
+    g = torch.zeros((3,) + shape, dtype=rdt, device="cuda")
+    capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), lout.data_ptr(), g.data_ptr(), 1)
+    torch.cuda.synchronize()
+    e = np.abs(lout.double().cpu().numpy() - lam_ref).max() / np.abs(lam_ref).max()
+    assert e <= 10 * tol, e
+    eg = np.abs(g.double().cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    assert eg <= 10 * tol, eg
+    lat.close()
+
+
+def _channel_problem(shape, steps, storage):
+    rho0, u0 = _init(shape, 11)
+    o = Oracle(shape, 0.8, faces=FACES)
+    f0 = o.init(rho0, u0)
+    F = wl.normal_field(shape, 1e-6, 1)
+    hidden = wl.normal_field(shape, 1e-6, 2)
+    _, ut, _ = o.macro(o.run(f0, steps, hidden), hidden)
+    lat0 = Lattice(shape, 0.8, storage, "swap2", NAMES, rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0))
+    f0_dev = lat0.f.clone()
+    lat0.close()
+    return o, f0, F, ut, f0_dev
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_force_gradient_matches_oracle_adjoint(storage):
+    shape, steps = (16, 12, 10), 12
+    o, f0, F, ut, f0_dev = _channel_problem(shape, steps, storage)
+    L_ref, g_ref = o.loss_and_grad(f0, F, ut, steps)
+    spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=4)
+    L, g = force_gradient(torch.as_tensor(F, device="cuda"), f0_dev, spec, torch.as_tensor(ut, device="cuda"))
+    g = g.double().cpu().numpy()
+    assert abs(L - L_ref) <= (1e-10 if storage == "f64" else 1e-3) * L_ref
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"{storage}: gradient error vs oracle adjoint {err:.3e}")
+    assert err <= (1e-10 if storage == "f64" else 1e-3)
+
+
+def test_force_gradient_matches_central_differences_fp64():
+    # FD in FP64 on the GPU path (eps 1e-4 on the force), like the adjoint workload, smaller
+    shape, steps = (16, 12, 10), 12
+    o, f0, F, ut, f0_dev = _channel_problem(shape, steps, "f64")
+    spec = dict(shape=shape, tau=0.8, storage="f64", faces=NAMES, steps=steps, checkpoint=4)
+    Ft = torch.as_tensor(F, device="cuda")
+    utt = torch.as_tensor(ut, device="cuda")
+    _, g = force_gradient(Ft, f0_dev, spec, utt)
+    g = g.cpu().numpy()
+    from paper_2208_05429_amd.adjoint import ForceAdjoint
+
+    def fd(x, y, z, a, eps):
+        vals = []
+        for sgn in (1, -1):
+            Fp = Ft.clone()
+            Fp[a, x, y, z] += sgn * eps
+            u = ForceAdjoint.apply(Fp, f0_dev, spec)
+            vals.append(float(((u - utt) ** 2).sum()))
+        return (vals[0] - vals[1]) / (2 * eps)
+
+    gmax = np.abs(g).max()
+    for (x, y, z) in wl.sample_cells(shape, 4, 3):
+        for a in range(3):
+            # the loss is not quadratic in F: central differences at the
+            # workload's eps = 1e-4 carry an O(eps^2) term (up to 1e-4 of
+            # max|grad| here); Richardson extrapolation over eps, eps/2 removes it
+            d1, d2 = fd(x, y, z, a, 1e-4), fd(x, y, z, a, 5e-5)
+            assert abs(d1 - g[a, x, y, z]) <= 2e-4 * gmax, (x, y, z, a)
+            assert abs((4 * d2 - d1) / 3 - g[a, x, y, z]) <= 1e-6 * gmax, (x, y, z, a)

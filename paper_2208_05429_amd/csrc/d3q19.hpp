@@ -170,6 +170,37 @@ __device__ __forceinline__ R wall_term(R uwx, R uwy, R uwz)
     return w6 * cu;
 }
 
+// The moving-wall term, written into a table of Q values (entry q: the term
+// received in direction q; entry 0 is zero), for kernels that keep it in LDS.
+template <class R>
+__device__ __forceinline__ void wall_terms_to(R* tab, int lane, R uwx, R uwy, R uwz)
+{
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if (lane == q) tab[q] = (q == 0) ? R(0) : wall_term<q>(uwx, uwy, uwz);
+    });
+}
+
+// Moving wall, applied at the source.  A population whose link leaves the
+// domain through the moving face has exactly one reader: the bounce-back
+// into the opposite direction of its own cell.  Adding the wall term to it
+// right after the collision is therefore the same single addition as adding
+// it on receipt.  rmask: receiving directions q of this cell whose source lies
+// beyond the moving face (bit q set: the cell's outgoing opp(q) gets term q).
+// The table is read through a volatile pointer so the Q terms are loaded
+// where they are used, on the few boundary lanes, instead of being kept live
+// across the whole march.
+template <class R>
+__device__ __forceinline__ void moving_wall_out(R (&v)[Q], uint32_t rmask, const R* tab)
+{
+    if (rmask == 0u) return;
+    const volatile R* t = tab;
+    sfor<1, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if ((rmask >> q) & 1u) v[oppq(q)] += t[q];
+    });
+}
+
 // ---- per-cell physics in offset form ----
 //
 // With g_q = f_q - w_q: rho = 1 + sum g, j = sum c g, u = (j + F/2)/rho and

@@ -63,13 +63,22 @@ bool march_shape_of(int storage, int M, int variant, int nz, MarchPlan* r)
                                      : int(sizeof(kShapesF32) / sizeof(ShapeEntry));
     int idx = 2 * variant + (M == 2 ? 0 : 1);
     if (variant < 0 || idx >= n || tab[idx].M != M) return false;
-    // pairs of z-adjacent cells need an even row length: use the next (plain) entry
-    if (tab[idx].pr && (nz % 2) != 0) idx += 2;
-    if (idx >= n || tab[idx].M != M) return false;
+    // pairs of z-adjacent cells need an even row length: take the plain-layout
+    // entry of the same tile (or else the first plain entry) for odd nz
+    if (tab[idx].pr && (nz % 2) != 0) {
+        int alt = -1;
+        for (int j = 0; j < n && alt < 0; ++j)
+            if (!tab[j].pr && tab[j].M == M && tab[j].TY == tab[idx].TY && tab[j].TZ == tab[idx].TZ) alt = j;
+        for (int j = 0; j < n && alt < 0; ++j)
+            if (!tab[j].pr && tab[j].M == M) alt = j;
+        if (alt < 0) return false;
+        idx = alt;
+    }
     r->TY = tab[idx].TY;
     r->TZ = tab[idx].TZ;
     r->NT = tab[idx].NT;
     r->pr = tab[idx].pr;
+    r->pf = tab[idx].pf;
     return true;
 }
 

@@ -24,6 +24,7 @@ struct MarchPlan {
     int M = 0;
     int TY = 0, TZ = 0, NT = 0;  // interior tile and threads per workgroup
     int pr = 0;                  // 1: pair-and-ring kernel layout
+    int pf = 1;                  // planes the loads run ahead
     int nty = 0, ntz = 0;        // tiles along y and z
     int nseg = 0, seg_len = 0;   // x segments
     int ry = 1, rz = 1;          // neighbourhood radius (in tiles) of the hazard check

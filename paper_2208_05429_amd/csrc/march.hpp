@@ -87,12 +87,11 @@ __device__ __forceinline__ void complete(R (&acc)[Q], const R* __restrict__ X, i
 // deposit(): after acc[] was consumed, refill it with what is known of plane
 // p (c_x = 0 populations, bounce-backs, and the c_x = +1 populations received
 // one iteration earlier in nxt[]) and put plane p+1's c_x = +1 populations in
-// nxt[].  bnext: directions of plane p whose source is beyond a wall; mnext:
-// those among them that cross the moving face.
+// nxt[].  bnext: directions of plane p whose source is beyond a wall (a
+// moving wall's term was already added at the source, see moving_wall_out).
 template <class R, bool WALLS>
 __device__ __forceinline__ void deposit(R (&acc)[Q], R (&nxt)[5], const R* __restrict__ X, int stride, int ci,
-                                        int wz, R o0, R o1, R o10, uint32_t bnext, uint32_t mnext, R uwx, R uwy,
-                                        R uwz)
+                                        int wz, R o0, R o1, R o10, uint32_t bnext)
 {
     sfor<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -103,7 +102,6 @@ __device__ __forceinline__ void deposit(R (&acc)[Q], R (&nxt)[5], const R* __res
                 bval = X[yz_index(qo) * stride + ci];
             else
                 bval = (qo == 1) ? o1 : o10;
-            if ((mnext >> q) & 1u) bval += wall_term<q>(uwx, uwy, uwz);
         }
         if constexpr (cxq(q) == 0) {
             R rv;
@@ -146,6 +144,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
     __shared__ R X1[NB1][16 * NC];
     __shared__ R X2[(M == 2) ? 16 * NC2 : 1];
+    __shared__ R WT[WALLS ? Q : 1];  // moving-wall terms (entry q: received along c_q)
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
@@ -161,7 +160,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     const bool has_next = !wallx || seg + 1 < a.nseg;
     const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
     const R omega = R(g.omega);
-    const R uwx = R(g.uw[0]), uwy = R(g.uw[1]), uwz = R(g.uw[2]);
+    if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
     const long long N = g.N, PL = g.PL;
 
     // ---- columns owned by this thread ----
@@ -391,6 +390,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) o1[k][c] = o1p[k][c] = o2[k][c] = R(0);
+    if constexpr (WALLS) __syncthreads();  // the wall-term table is complete
     const int total = (e - s) + 2 * M + 1;
     issue_load(s - M, true);
     int seen = poll_issue();
@@ -405,6 +405,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         // ---- A: step-1 collide of plane xl, then the loads of plane xl+1 ----
         R Fs[K][3];
         const bool pres = present(xl);
+        const uint32_t xmc = xm(xl);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if constexpr (FORCE) {
@@ -416,6 +417,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 #pragma unroll
                 for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
                 collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+                if constexpr (WALLS) moving_wall_out(v, myz[k] | xmc, WT);
                 const int c = tid + k * NT;
                 sfor<0, Q>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         if (storing) poll_finish(seen, i, r_out);
         {
             const int p = xl - M;  // plane collided by the last step one iteration ago
-            const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
+            const uint32_t xbd = xb(p - 1), xbn = xb(p);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool act = rad[k] == 0 && gofs[k] >= 0;
@@ -441,14 +443,14 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     store(acc2[k], k, r_out, storing);
                     if (act)
                         deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
-                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+                                          byz[k] | xbn);
                 } else {
                     const int c = tid + k * NT;
                     if (act) complete<R, WALLS>(acc1[k], X1r, NC, c, WZ, o1p[k][1], byz[k] | xbd);
                     store(acc1[k], k, r_out, storing);
                     if (act)
                         deposit<R, WALLS>(acc1[k], nxt1[k], X1r, NC, c, WZ, o1p[k][0], o1p[k][1], o1p[k][2],
-                                          byz[k] | xbn, myz[k] | xmn, uwx, uwy, uwz);
+                                          byz[k] | xbn);
                 }
             }
         }
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
-            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
+            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmc2 = xm(xl - 1);
             const bool coll2 = i >= M && present(xl - 1);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -473,6 +475,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     complete<R, WALLS>(acc1[k], X1w, NC, c, WZ, o1[k][1], byz[k] | xbd1);
                     if (coll2) {
                         collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        if constexpr (WALLS) moving_wall_out(acc1[k], myz[k] | xmc2, WT);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
                             if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = acc1[k][q];
@@ -482,7 +485,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                         o2[k][2] = acc1[k][10];
                     }
                     deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, c, WZ, o1[k][0], o1[k][1], o1[k][2],
-                                      byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
+                                      byz[k] | xbn1);
                 }
                 if constexpr (FORCE) {
 #pragma unroll

@@ -12,7 +12,7 @@ template <int S, int M, int TY, int TZ, int NT, bool ALLOW_FORCE>
 struct Shape {
     static bool match(const MarchPlan& p)
     {
-        return p.pr == 0 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+        return p.pr == 0 && p.pf == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
     }
     static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
     {
@@ -40,37 +40,39 @@ struct Shape {
     }
 };
 
-// A pair-and-ring shape (march_pr.hpp): NT = TY*TZ/2, needs an even nz.
-template <int S, int M, int TY, int TZ, bool ALLOW_FORCE>
+// A pair-and-ring shape (march_pr.hpp): NT = TY*TZ/2, needs an even nz.  PF is
+// how many planes ahead the loads run; a body force always uses PF = 1 (its
+// extra registers leave no room for a second plane of loads).
+template <int S, int M, int TY, int TZ, bool ALLOW_FORCE, int PF = 1>
 struct PRShape {
     static constexpr int NT = TY * TZ / 2;
     static bool match(const MarchPlan& p)
     {
-        return p.pr == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+        return p.pr == 1 && p.pf == PF && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
     }
     static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
     {
         if constexpr (ALLOW_FORCE) {
             if (force)
-                return walls ? launch_march_pr_shape<S, M, TY, TZ, true, true>(p, a, s)
-                             : launch_march_pr_shape<S, M, TY, TZ, false, true>(p, a, s);
+                return walls ? launch_march_pr_shape<S, M, TY, TZ, true, true, 1>(p, a, s)
+                             : launch_march_pr_shape<S, M, TY, TZ, false, true, 1>(p, a, s);
         } else {
             if (force) return hipErrorInvalidValue;
         }
-        return walls ? launch_march_pr_shape<S, M, TY, TZ, true, false>(p, a, s)
-                     : launch_march_pr_shape<S, M, TY, TZ, false, false>(p, a, s);
+        return walls ? launch_march_pr_shape<S, M, TY, TZ, true, false, PF>(p, a, s)
+                     : launch_march_pr_shape<S, M, TY, TZ, false, false, PF>(p, a, s);
     }
     static int max_blocks(bool walls, bool force)
     {
         if constexpr (ALLOW_FORCE) {
             if (force)
-                return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, true>()
-                             : max_blocks_pr_shape<S, M, TY, TZ, false, true>();
+                return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, true, 1>()
+                             : max_blocks_pr_shape<S, M, TY, TZ, false, true, 1>();
         } else {
             if (force) return 0;
         }
-        return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, false>()
-                     : max_blocks_pr_shape<S, M, TY, TZ, false, false>();
+        return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, false, PF>()
+                     : max_blocks_pr_shape<S, M, TY, TZ, false, false, PF>();
     }
 };
 
@@ -92,16 +94,18 @@ struct ShapeList {
     }
 };
 
-// Shapes per storage type, {M, TY, TZ, NT, pair_ring}, in variant order
-// (variant v uses entries 2v (M = 2) and 2v+1 (M = 1)).  Pair-and-ring
-// shapes need an even nz; the planner falls back to variant 1 otherwise.
+// Shapes per storage type, {M, TY, TZ, NT, pair_ring, prefetch planes}, in
+// variant order (variant v uses entries 2v (M = 2) and 2v+1 (M = 1)).
+// Pair-and-ring shapes need an even nz; the planner falls back to variant 1
+// (plain layout) otherwise.
 struct ShapeEntry {
-    int M, TY, TZ, NT, pr;
+    int M, TY, TZ, NT, pr, pf;
 };
-constexpr ShapeEntry kShapesF64[] = {{2, 12, 28, 512, 0}, {1, 14, 30, 512, 0}};
-constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1}, {1, 16, 64, 512, 1}, {2, 16, 64, 512, 0},
-                                     {1, 16, 64, 512, 0}, {2, 32, 32, 512, 1}, {1, 32, 32, 512, 1},
-                                     {2, 32, 32, 512, 0}, {1, 32, 32, 512, 0}};
+constexpr ShapeEntry kShapesF64[] = {{2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}};
+constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}, {2, 16, 64, 512, 0, 1},
+                                     {1, 16, 64, 512, 0, 1}, {2, 32, 32, 512, 1, 1}, {1, 32, 32, 512, 1, 1},
+                                     {2, 32, 32, 512, 0, 1}, {1, 32, 32, 512, 0, 1}, {2, 16, 64, 512, 1, 2},
+                                     {1, 16, 64, 512, 1, 2}};
 
 hipError_t launch_march_f64(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
 hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);

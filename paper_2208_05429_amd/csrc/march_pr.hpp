@@ -28,17 +28,27 @@
 
 namespace lbm {
 
-// two z-adjacent values of one direction: one 8-byte (32-bit storage) or
-// 4-byte (16-bit storage) access
+// Two z-adjacent values of one direction, moved as one access: 8 bytes for
+// 32-bit storage, 4 bytes for 16-bit storage.  P is how a loaded pair waits in
+// registers until it is decoded: two floats, or both 16-bit codes packed in
+// one register (half the registers for a plane of loads in flight).
 template <class T>
 struct Buf2;
 template <>
 struct Buf2<float> {
-    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float& a, float& b)
+    struct P {
+        float a, b;
+    };
+    static __device__ __forceinline__ P ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
     {
         auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-        a = __uint_as_float(v[0]);
-        b = __uint_as_float(v[1]);
+        return P{__uint_as_float(v[0]), __uint_as_float(v[1])};
+    }
+    static __device__ __forceinline__ P zero() { return P{0.0f, 0.0f}; }
+    template <int K>
+    static __device__ __forceinline__ float get(P p)
+    {
+        return K == 0 ? p.a : p.b;
     }
     static __device__ __forceinline__ void st(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t off)
     {
@@ -51,11 +61,16 @@ struct Buf2<float> {
 };
 template <>
 struct Buf2<uint16_t> {
-    static __device__ __forceinline__ void ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t& a, uint16_t& b)
+    typedef uint32_t P;
+    static __device__ __forceinline__ P ld(__amdgpu_buffer_rsrc_t r, uint32_t off)
     {
-        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-        a = uint16_t(v & 0xffffu);
-        b = uint16_t(v >> 16);
+        return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ P zero() { return 0u; }
+    template <int K>
+    static __device__ __forceinline__ uint16_t get(P p)
+    {
+        return K == 0 ? uint16_t(p & 0xffffu) : uint16_t(p >> 16);
     }
     static __device__ __forceinline__ void st(uint16_t a, uint16_t b, __amdgpu_buffer_rsrc_t r, uint32_t off)
     {
@@ -104,7 +119,7 @@ __device__ __forceinline__ void complete_s(R (&acc)[Q], const R* __restrict__ X,
 
 template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
 __device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], const R* __restrict__ X, int ci, R o0, R o1,
-                                          R o10, uint32_t bnext, uint32_t mnext, R uwx, R uwy, R uwz)
+                                          R o10, uint32_t bnext)
 {
     constexpr int HALF = STRIDE / 2;
     sfor<0, Q>([&](auto qc) {
@@ -116,7 +131,6 @@ __device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], const R* __r
                 bval = X[yz_index(qo) * STRIDE + split_at<PAR, HALF>(ci, 0)];
             else
                 bval = (qo == 1) ? o1 : o10;
-            if ((mnext >> q) & 1u) bval += wall_term<q>(uwx, uwy, uwz);
         }
         if constexpr (cxq(q) == 0) {
             R rv;
@@ -174,7 +188,7 @@ __device__ __forceinline__ void ring_cell(int r, int& ly, int& lz)
     }
 }
 
-template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE>
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
 __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 {
     using Cd = Codec<S>;
@@ -186,9 +200,11 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
     static_assert(M == 1 || M == 2, "one or two merged steps");
     static_assert(sizeof(T) == 2 || sizeof(T) == 4, "32-bit arithmetic storages");
+    static_assert(PF == 1 || PF == 2, "loads run one or two planes ahead");
 
     __shared__ R X1[NB1][16 * NC];
     __shared__ R X2[(M == 2) ? 16 * NC2 : 1];
+    __shared__ R WT[WALLS ? Q : 1];  // moving-wall terms (entry q: received along c_q)
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
@@ -204,7 +220,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     const bool has_next = !wallx || seg + 1 < a.nseg;
     const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
     const R omega = R(g.omega);
-    const R uwx = R(g.uw[0]), uwy = R(g.uw[1]), uwz = R(g.uw[2]);
+    if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
     const long long N = g.N, PL = g.PL;
 
     // ---- the three columns of this thread: 0, 1 = interior pair, 2 = ring ----
@@ -285,8 +301,10 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
 
     // ---- pipeline registers ----
-    T Lr[K][Q];
-    R Fl1[K][3], Fl2[K][3];
+    using P2 = typename Buf2<T>::P;
+    P2 Lp[PF][Q];  // raw pair loads, PF planes in flight
+    T Lg[PF][Q];   // raw ring loads
+    R Fl1[PF][K][3], Fl2[K][3];
     R acc1[K][Q], nxt1[K][5];  // step 1: pair and ring
     R acc2[2][Q], nxt2[2][5];  // last step of M = 2: pair only
     R o1[K][3], o2[K][3];
@@ -294,7 +312,6 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     for (int k = 0; k < K; ++k) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            Lr[k][q] = T(0);
             acc1[k][q] = R(0);
             if (k < 2) acc2[k][q] = R(0);
         }
@@ -304,8 +321,20 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             if (k < 2) nxt2[k][j] = R(0);
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Fl1[k][c] = Fl2[k][c] = o1[k][c] = o2[k][c] = R(0);
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int b = 0; b < PF; ++b) Fl1[b][k][c] = R(0);
+            Fl2[k][c] = o1[k][c] = o2[k][c] = R(0);
+        }
     }
+
+#pragma unroll
+    for (int b = 0; b < PF; ++b)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Lp[b][q] = Buf2<T>::zero();
+            Lg[b][q] = T(0);
+        }
 
     T* __restrict__ f = static_cast<T*>(a.f);
     const T* __restrict__ side = static_cast<const T*>(a.side);
@@ -323,44 +352,44 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         qstride = N;
         return f + (long long)wrapi(xp, g.nx) * PL;
     };
-    auto load_force = [&](int xp, bool live, int k, uint32_t off) {
+    auto load_force = [&](int xp, bool live, R (&Fb)[3], uint32_t off) {
         if constexpr (FORCE) {
             const uint32_t rangeR = live ? uint32_t(PL) * uint32_t(sizeof(R)) : 0u;
             const R* bc = F + (long long)wrapi(xp, g.nx) * PL;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Fl1[k][c] = Buf<R>::ld(make_rsrc(bc, rangeR), off);
+                Fb[c] = Buf<R>::ld(make_rsrc(bc, rangeR), off);
                 bc += N;
             }
         }
     };
-    auto load_pair = [&](int xp, bool wanted) {
+    auto load_pair = [&](int xp, bool wanted, P2 (&L)[Q], R (&Fb)[K][3]) {
         const bool live = wanted && present(xp);
         long long qs;
         const T* bq = plane_base(xp, qs);
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            Buf2<T>::ld(make_rsrc(bq, range), loffP, Lr[0][q], Lr[1][q]);
+            L[q] = Buf2<T>::ld(make_rsrc(bq, range), loffP);
             bq += qs;
         }
         if constexpr (FORCE) {
-            load_force(xp, live, 0, loffPR);
+            load_force(xp, live, Fb[0], loffPR);
             const uint32_t off1 = loffPR == kOffNone ? kOffNone : loffPR + uint32_t(sizeof(R));
-            load_force(xp, live, 1, off1);
+            load_force(xp, live, Fb[1], off1);
         }
     };
-    auto load_ring = [&](int xp, bool wanted) {
+    auto load_ring = [&](int xp, bool wanted, T (&L)[Q], R (&Fb)[K][3]) {
         const bool live = wanted && present(xp);
         long long qs;
         const T* bq = plane_base(xp, qs);
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            Lr[2][q] = Buf<T>::ld(make_rsrc(bq, range), loffG);
+            L[q] = Buf<T>::ld(make_rsrc(bq, range), loffG);
             bq += qs;
         }
-        load_force(xp, live, 2, loffGR);
+        load_force(xp, live, Fb[2], loffGR);
     };
 
     // hazard check (see march.hpp): every wave reads the counters of the
@@ -419,11 +448,19 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         }
     };
 
-    auto collide1 = [&](int k, R* X1w) {
+    // step-1 collide of column k from its raw values (decoded here)
+    auto collide1 = [&](auto kc, R* X1w, const P2 (&LP)[Q], const T (&LG)[Q], const R (&Fb)[K][3], uint32_t mwall) {
+        constexpr int k = decltype(kc)::value;
         R v[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
-        collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+        for (int q = 0; q < Q; ++q) {
+            if constexpr (k < 2)
+                v[q] = Cd::dec(Buf2<T>::template get<k>(LP[q]));
+            else
+                v[q] = Cd::dec(LG[q]);
+        }
+        collide<R, FORCE>(v, omega, Fb[k][0], Fb[k][1], Fb[k][2]);
+        if constexpr (WALLS) moving_wall_out(v, mwall, WT);
         const int sl = ((ci[k] & 1) ? NC / 2 : 0) + (ci[k] >> 1);
         sfor<0, Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
@@ -434,15 +471,22 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         o1[k][2] = v[10];
     };
 
+    if constexpr (WALLS) __syncthreads();  // the wall-term table is complete
     const int total = (e - s) + 2 * M;
-    load_pair(s - M, true);
-    load_ring(s - M, true);
-    for (int i = 0; i < total; ++i) {
+    // prologue: the first PF planes; iteration i consumes buffer i % PF and
+    // refills it with plane xl + PF
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
+        load_pair(s - M + b, b < total, Lp[b], Fl1[b]);
+        load_ring(s - M + b, b < total, Lg[b], Fl1[b]);
+    }
+    auto iteration = [&](auto pbc, int i) {
+        constexpr int pb = decltype(pbc)::value;
         const int xl = s - M + i;
         R* X1w = X1[(M == 1) ? (i & 1) : 0];
         const int r_out = xl - M;
         const bool storing = r_out >= s && r_out < e;
-        const bool next_wanted = i + 1 < total;
+        const bool next_wanted = i + PF < total;
         const int seen = __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         // ---- A: step-1 collide of plane xl; loads of plane xl+1 follow each column ----
@@ -451,20 +495,24 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
+                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[pb][k][c];
         }
         const bool pres = present(xl);
-        if (pres && rad[0] <= M && gofs[0] >= 0) collide1(0, X1w);
-        if (pres && rad[1] <= M && gofs[1] >= 0) collide1(1, X1w);
-        load_pair(xl + 1, next_wanted);
-        if (pres && rad[2] <= M && gofs[2] >= 0) collide1(2, X1w);
-        load_ring(xl + 1, next_wanted);
+        const uint32_t xmc = xm(xl);
+        if (pres && rad[0] <= M && gofs[0] >= 0)
+            collide1(std::integral_constant<int, 0>{}, X1w, Lp[pb], Lg[pb], Fl1[pb], myz[0] | xmc);
+        if (pres && rad[1] <= M && gofs[1] >= 0)
+            collide1(std::integral_constant<int, 1>{}, X1w, Lp[pb], Lg[pb], Fl1[pb], myz[1] | xmc);
+        load_pair(xl + PF, next_wanted, Lp[pb], Fl1[pb]);
+        if (pres && rad[2] <= M && gofs[2] >= 0)
+            collide1(std::integral_constant<int, 2>{}, X1w, Lp[pb], Lg[pb], Fl1[pb], myz[2] | xmc);
+        load_ring(xl + PF, next_wanted, Lg[pb], Fl1[pb]);
         __syncthreads();
         if (tid == 0) __hip_atomic_store(a.flags + (1 + (long long)wid) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
-            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
+            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmc2 = xm(xl - 1);
             const bool coll2 = i >= M && present(xl - 1);
             sfor<0, K>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
@@ -474,6 +522,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                     complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], byz[k] | xbd1);
                     if (coll2) {
                         collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        if constexpr (WALLS) moving_wall_out(acc1[k], myz[k] | xmc2, WT);
                         const int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
@@ -484,7 +533,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                         o2[k][2] = acc1[k][10];
                     }
                     deposit_s<R, WALLS, PAR, NC, WZ>(acc1[k], nxt1[k], X1w, ci[k], o1[k][0], o1[k][1], o1[k][2],
-                                                     byz[k] | xbn1, myz[k] | xmn1, uwx, uwy, uwz);
+                                                     byz[k] | xbn1);
                 }
                 if constexpr (FORCE) {
 #pragma unroll
@@ -497,7 +546,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         // ---- D: last-step receive of the pair, hazard check, in-place store ----
         {
             const int p = xl - M + 1;  // plane the last step collided
-            const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
+            const uint32_t xbd = xb(p - 1), xbn = xb(p);
             const bool act = rad[0] == 0 && gofs[0] >= 0;
             if constexpr (M == 2) {
                 if (act) {
@@ -508,9 +557,9 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 store_pair(acc2[0], acc2[1], r_out, storing);
                 if (act) {
                     deposit_s<R, WALLS, 1, NC2, WZ2>(acc2[0], nxt2[0], X2, ci2[0], o2[0][0], o2[0][1], o2[0][2],
-                                                     byz[0] | xbn, myz[0] | xmn, uwx, uwy, uwz);
+                                                     byz[0] | xbn);
                     deposit_s<R, WALLS, 0, NC2, WZ2>(acc2[1], nxt2[1], X2, ci2[1], o2[1][0], o2[1][1], o2[1][2],
-                                                     byz[1] | xbn, myz[1] | xmn, uwx, uwy, uwz);
+                                                     byz[1] | xbn);
                 }
             } else {
                 if (act) {
@@ -521,32 +570,38 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 store_pair(acc1[0], acc1[1], r_out, storing);
                 if (act) {
                     deposit_s<R, WALLS, 1, NC, WZ>(acc1[0], nxt1[0], X1w, ci[0], o1[0][0], o1[0][1], o1[0][2],
-                                                   byz[0] | xbn, myz[0] | xmn, uwx, uwy, uwz);
+                                                   byz[0] | xbn);
                     deposit_s<R, WALLS, 0, NC, WZ>(acc1[1], nxt1[1], X1w, ci[1], o1[1][0], o1[1][1], o1[1][2],
-                                                   byz[1] | xbn, myz[1] | xmn, uwx, uwy, uwz);
+                                                   byz[1] | xbn);
                 }
             }
+        }
+    };
+    for (int i = 0; i < total; i += PF) {
+        iteration(std::integral_constant<int, 0>{}, i);
+        if constexpr (PF == 2) {
+            if (i + 1 < total) iteration(std::integral_constant<int, 1>{}, i + 1);
         }
     }
 }
 
-template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE>
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
 hipError_t launch_march_pr_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
 {
-    auto kern = k_march_pr<S, M, TY, TZ, WALLS, FORCE>;
+    auto kern = k_march_pr<S, M, TY, TZ, WALLS, FORCE, PF>;
     MarchArgs arg = a;
     void* params[] = {&arg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks),
                                       dim3(PairRingShape<M, TY, TZ>::NT), params, 0, st);
 }
 
-template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE>
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
 int max_blocks_pr_shape()
 {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_pr<S, M, TY, TZ, WALLS, FORCE>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_pr<S, M, TY, TZ, WALLS, FORCE, PF>,
                                                      PairRingShape<M, TY, TZ>::NT, 0) != hipSuccess)
         return 0;
     return per_cu * cus;

@@ -103,7 +103,8 @@ CASES = [
     ((19, 35, 130), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
     ((21, 18, 66), (PERIODIC, PERIODIC, WALL, WALL, MOVING_WALL, WALL), (0.03, -0.02, 0.0)),
 ]
-VARIANTS = [0, 1, 2, 3]  # 32-bit storages: 16x64 pair-ring, 16x64 slots, 32x32 pair-ring, 32x32 slots
+VARIANTS = [0, 1, 2, 3, 4]  # 32-bit storages: 16x64 pair-ring, 16x64 slots, 32x32 pair-ring, 32x32 slots,
+# 16x64 pair-ring with loads two planes ahead
 
 
 def _noisy_init(shape, seed):

@@ -110,6 +110,17 @@ lbm_status lbm_attach(const lbm_config* cfg, void* f_dev, void* work_dev, const 
  * LBM_TWO_ARRAY copies the state back into f_dev after an odd number of steps. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* Advance k in {1, 2} steps from the state f_src into f_dst, out of place:
+ * f_src is read only and the context's own distribution buffer is neither
+ * read nor changed.  Both buffers have the size and layout of f (19N values
+ * of the storage type), must not overlap and must be 256-byte aligned.  With
+ * LBM_SWAP2 and k = 2 this is one merged pass, the same kernel and the same
+ * bytes moved as an in-place pass (no side planes or progress counters are
+ * needed: nothing is overwritten that is still to be read).  Used by the
+ * adjoint's recomputation of the states of a checkpoint interval, which
+ * then needs no copies. */
+lbm_status lbm_step_into(lbm_ctx* ctx, const void* f_src, void* f_dst, int32_t k);
+
 /* Per-cell density, velocity u = (sum c f + F/2)/rho and velocity norm |u|
  * (the quantity compared across algorithms in Sec. 5.1), all as doubles
  * computed in double from the stored state.  rho_dev: N, u_dev: 3N (SoA),
@@ -131,8 +142,13 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
  * (storage type and layout of f, left unchanged): lambda_in_dev holds
  * dL/df_{t+k}; lambda_out_dev receives dL/df_t (distinct buffers, 19N of the
  * arithmetic type); grad_force_dev (3N) accumulates the force gradient of the
- * k steps.  With k = 2 the state f_{t+1} is recomputed on chip, so one call
- * reads f_t once (the adjoint of the two-step merged pass). */
+ * k steps (required with a force, may be NULL without).  The reverse of the
+ * step of Sec. 3: the transposed stream gathers lambda_q from the link's
+ * target (the own lambda of the opposite direction on a wall link), then the
+ * transposed collision acts per cell.  With k = 2 the state f_{t+1} is
+ * recomputed on chip, so one call reads f_t once: the adjoint of the two-step
+ * merged pass of Sec. 4.1 (132 bytes per lattice update at FP32).  FP64 and
+ * FP32 storage only (LBM_EUNSUPPORTED otherwise). */
 lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambda_in_dev, void* lambda_out_dev,
                             void* grad_force_dev, int32_t k);
 

@@ -3,9 +3,12 @@ body force, through the library's discrete adjoint (argument marshalling only).
 
 Forward: T time steps from f0 under the Guo force F, keeping the state every
 `checkpoint` steps.  Backward: lambda_T = dL/df_T from dL/du (lbm_macro_adjoint,
-which also adds the direct dL/dF), then for each checkpoint segment in
-reverse: restore the checkpoint, recompute the segment's states, and run the
-adjoint of each step backwards (lbm_step_adjoint), accumulating dL/dF.
+which also adds the direct dL/dF), then for each checkpoint interval in
+reverse: recompute the states the reverse steps start from (lbm_step_into,
+out of place, so no state is ever copied), and run the adjoint backwards
+(lbm_step_adjoint), accumulating dL/dF.  With spec["merged"] the reverse
+steps go two at a time (the adjoint of the merged pass, f_{t+1} recomputed on
+chip), so only every other state is needed.
 """
 from __future__ import annotations
 
@@ -55,25 +58,35 @@ class ForceAdjoint(torch.autograd.Function):
         gu = grad_u.to(device=dev, dtype=rdt).contiguous()
         capi.lbm_set_stream(lat.ctx, torch.cuda.current_stream().cuda_stream)
         capi.lbm_macro_adjoint(lat.ctx, _ptr(lat.f), _ptr(gu), _ptr(lam), _ptr(gF))
+        pool = []  # state buffers reused across intervals
         for seg in range(len(ckpts) - 1, -1, -1):
-            t0 = seg * k
-            n = min(k, steps - t0)
-            lat.f.copy_(ckpts[seg])
-            states = [ckpts[seg]]
-            for _ in range(n - 1):
-                lat.step(1)
-                states.append(lat.f.clone())
-            t = n
-            while t > 0:
-                if merged and t >= 2:
-                    capi.lbm_step_adjoint(lat.ctx, _ptr(states[t - 2]), _ptr(lam), _ptr(lam2), _ptr(gF), 2)
-                    t -= 2
-                else:
-                    capi.lbm_step_adjoint(lat.ctx, _ptr(states[t - 1]), _ptr(lam), _ptr(lam2), _ptr(gF), 1)
-                    t -= 1
+            n = min(k, steps - seg * k)
+            calls = reverse_schedule(n, merged)
+            need = sorted({t0 for t0, _ in calls})
+            states = {0: ckpts[seg]}
+            prev = 0
+            for j, t0 in enumerate(t for t in need if t > 0):
+                while len(pool) <= j:
+                    pool.append(torch.empty_like(lat.f))
+                lat.step_into(states[prev], pool[j], t0 - prev)
+                states[t0] = pool[j]
+                prev = t0
+            for t0, kk in calls:
+                capi.lbm_step_adjoint(lat.ctx, _ptr(states[t0]), _ptr(lam), _ptr(lam2), _ptr(gF), kk)
                 lam, lam2 = lam2, lam
         F, = ctx.saved_tensors
         return gF.to(F.dtype), None, None
+
+
+def reverse_schedule(n, merged):
+    """Reverse steps of an interval of n steps, latest first, as (start, k):
+    the adjoint of steps start .. start+k-1 of the interval."""
+    calls, t = [], n
+    while t > 0:
+        kk = 2 if merged and t >= 2 else 1
+        calls.append((t - kk, kk))
+        t -= kk
+    return calls
 
 
 def force_gradient(F, f0, spec, u_target):

@@ -51,6 +51,7 @@ def lib():
         L.lbm_init.argtypes = [cfgp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.lbm_attach.argtypes = [cfgp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.lbm_step.argtypes = [_vp, ctypes.c_int64]
+        L.lbm_step_into.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.lbm_macroscopic.argtypes = [_vp, _vp, _vp, _vp, dp]
         L.lbm_macro_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.lbm_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32]
@@ -61,7 +62,7 @@ def lib():
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_destroy.argtypes = [_vp]
         L.lbm_destroy.restype = None
-        for name in ("lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_macroscopic",
+        for name in ("lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_step_into", "lbm_macroscopic",
                      "lbm_macro_adjoint", "lbm_step_adjoint", "lbm_set_stream", "lbm_set_kernel_timing",
                      "lbm_kernel_time"):
             getattr(L, name).restype = ctypes.c_int
@@ -118,6 +119,10 @@ def lbm_attach(cfg, f_dev, work_dev, force_dev, stream):
 
 def lbm_step(ctx, n):
     _check(lib().lbm_step(ctx, int(n)), ctx)
+
+
+def lbm_step_into(ctx, f_src_dev, f_dst_dev, k):
+    _check(lib().lbm_step_into(ctx, f_src_dev, f_dst_dev, int(k)), ctx)
 
 
 def lbm_macroscopic(ctx, rho_dev, u_dev, unorm_dev, want_sums=False):

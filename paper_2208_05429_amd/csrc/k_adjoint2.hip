@@ -1,0 +1,358 @@
+// k_adjoint2.hip -- the discrete adjoint of two merged time steps in one pass
+// over memory: lambda_t from lambda_{t+2}, the state f_t and the force F, with
+// the intermediate state f_{t+1} recomputed on chip.
+//
+// Two forward steps are f_{t+1} = S(C_t f_t), f_{t+2} = S(C_{t+1} f_{t+1}),
+// so the adjoint is
+//   lambda_{t+1} = C_{t+1}^T S^T lambda_{t+2},   lambda_t = C_t^T S^T lambda_{t+1},
+// and dL/dF gains the force terms of both transposed collisions (adjoint_core.hpp).
+//
+// The transposed stream is itself a stream.  S^T pulls lambda along +c
+// (mu_q(x) = lambda_q(x + c_q), or lambda_opp(q)(x) when the link leaves
+// through a wall).  Relabelled as nu_p = lambda_opp(p), that is the forward
+// push of nu with velocities c_p and the same halfway bounce-back (without a
+// moving-wall term, which is constant).  So all three exchanges of a pass --
+// the forward recompute f_t -> f_{t+1}, nu of lambda_{t+2} and nu of
+// lambda_{t+1} -- run through the same receive machinery as the forward
+// march (complete / deposit of march.hpp), three levels deep:
+//
+//   S1  plane P (front): collide f_t(P) on the tile plus a halo of two cells;
+//       its post-collision values and nu(lambda_{t+2}(P)) enter the exchange;
+//   S2  plane P-1 on the tile plus one halo cell: f_{t+1}(P-1) and
+//       mu(P-1) = S^T lambda_{t+2} are complete; lambda_{t+1}(P-1) =
+//       C_{t+1}^T mu enters the third exchange;
+//   S3  plane P-2 on the tile: mu = S^T lambda_{t+1} is complete, and
+//       lambda_t(P-2) = C_t^T mu (moments of f_t(P-2) kept from S1) is
+//       written out, together with the force gradient of both steps.
+//
+// The output is a separate buffer, so workgroups are independent: any number
+// of them, no co-residency and no progress counters.  Each owns a y-z tile
+// and an x segment and starts two planes early to fill its pipeline.
+// Bytes per cell and pass: f_t (19 s), lambda_{t+2} and lambda_t (2 x 19 x r),
+// F (3 r) and the read-modify-write of dL/dF (6 r); 132 B per lattice update
+// at FP32.
+#include "adjoint_core.hpp"
+#include "march.hpp"
+
+namespace lbm {
+
+// nu_p = v_opp(p): the relabelling between lambda and a forward-moving field
+template <class R>
+__device__ __forceinline__ void opp_relabel(const R (&src)[Q], R (&dst)[Q])
+{
+    sfor<0, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        dst[q] = src[oppq(q)];
+    });
+}
+
+template <int TY, int TZ>
+struct Adj2Shape {
+    static constexpr int WZ2 = TZ + 4, NC2 = (TY + 4) * WZ2;  // frame: tile plus two halo cells
+    static constexpr int WZ1 = TZ + 2, NC1 = (TY + 2) * WZ1;  // tile plus one halo cell
+};
+
+template <int S, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+__global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
+{
+    using Cd = Codec<S>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    using Sh = Adj2Shape<TY, TZ>;
+    constexpr int WZ2 = Sh::WZ2, NC2 = Sh::NC2, WZ1 = Sh::WZ1, NC1 = Sh::NC1;
+    static_assert(NC2 <= NT, "one frame column per thread");
+    constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
+
+    __shared__ R XF[16 * NC2];  // forward recompute: post-collision f_t
+    __shared__ R XA[16 * NC2];  // nu of lambda_{t+2}
+    __shared__ R XC[16 * NC1];  // nu of lambda_{t+1}
+    __shared__ R WT[WALLS ? Q : 1];
+
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+    const int wid = blockIdx.x;
+    const int tz = wid % a.ntz, ty = (wid / a.ntz) % a.nty, seg = wid / (a.ntz * a.nty);
+    const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
+    const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);
+    const bool wallx = g.wall[0] != 0;
+    const R omega = R(g.omega);
+    const long long N = g.N, PL = g.PL;
+    if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+
+    // ---- this thread's column of the frame ----
+    const int c = tid;
+    int gofs = -1, rad = 3, ci1 = 0;
+    uint32_t byz = 0, myz = 0;
+    if (c < NC2) {
+        const int ly = c / WZ2, lz = c - (c / WZ2) * WZ2;
+        if (ly < TYe + 4 && lz < TZe + 4) {
+            const int dy = ly < 2 ? 2 - ly : (ly >= 2 + TYe ? ly - (2 + TYe) + 1 : 0);
+            const int dz = lz < 2 ? 2 - lz : (lz >= 2 + TZe ? lz - (2 + TZe) + 1 : 0);
+            int y = ty * TY - 2 + ly, z = tz * TZ - 2 + lz;
+            bool inside = true;
+            if (g.wall[1]) inside = inside && y >= 0 && y < g.ny;
+            else y = wrapi(y, g.ny);
+            if (g.wall[2]) inside = inside && z >= 0 && z < g.nz;
+            else z = wrapi(z, g.nz);
+            if (inside) {
+                gofs = y * g.nz + z;
+                rad = dy > dz ? dy : dz;
+                ci1 = (ly - 1) * WZ1 + (lz - 1);
+                if constexpr (WALLS) {
+                    sfor<1, Q>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        if constexpr (moves_yz(q)) {
+                            const int ys = y - cyq(q), zs = z - czq(q);
+                            int f1 = -1, f2 = -1;
+                            if (g.wall[1] && ys < 0) f1 = 2;
+                            if (g.wall[1] && ys >= g.ny) f1 = 3;
+                            if (g.wall[2] && zs < 0) f2 = 4;
+                            if (g.wall[2] && zs >= g.nz) f2 = 5;
+                            if (f1 >= 0 || f2 >= 0) byz |= 1u << q;
+                            if (g.moving_face >= 0 && (f1 == g.moving_face || f2 == g.moving_face)) myz |= 1u << q;
+                        }
+                    });
+                }
+            }
+        }
+    }
+    const bool loads = rad <= 2 && gofs >= 0;
+    const uint32_t loffT = loads ? uint32_t(gofs) * uint32_t(sizeof(T)) : kOffNone;
+    const uint32_t loffR = loads ? uint32_t(gofs) * uint32_t(sizeof(R)) : kOffNone;
+    const uint32_t ooffR = (rad == 0 && gofs >= 0) ? uint32_t(gofs) * uint32_t(sizeof(R)) : kOffNone;
+
+    auto xb = [&](int p) -> uint32_t {
+        if (!wallx) return 0u;
+        return (p == 0 ? CXP : 0u) | (p == g.nx - 1 ? CXM : 0u);
+    };
+    auto xm = [&](int p) -> uint32_t {
+        if (!wallx) return 0u;
+        return ((p == 0 && g.moving_face == 0) ? CXP : 0u) | ((p == g.nx - 1 && g.moving_face == 1) ? CXM : 0u);
+    };
+    auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
+
+    // ---- registers of the three exchange levels and the histories ----
+    T Lf[Q];  // raw f_t of the next plane
+    R La[Q];  // lambda_{t+2} of the next plane
+    R Fl[3] = {R(0), R(0), R(0)}, gFl[3] = {R(0), R(0), R(0)};
+    R accA[Q], accB[Q], accC[Q], nxtA[5], nxtB[5], nxtC[5];
+    R oA[3], oB[3], oC[3];
+    R Fh1[3], Fh2[3], mh1[4], mh2[4], gFp[3];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        Lf[q] = T(0);
+        La[q] = accA[q] = accB[q] = accC[q] = R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) nxtA[j] = nxtB[j] = nxtC[j] = R(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) oA[j] = oB[j] = oC[j] = Fh1[j] = Fh2[j] = gFp[j] = R(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mh1[j] = mh2[j] = (j == 0 ? R(1) : R(0));
+
+    const T* __restrict__ ft = static_cast<const T*>(a.ft);
+    const R* __restrict__ F = static_cast<const R*>(a.F);
+    const R* __restrict__ lin = static_cast<const R*>(a.lin);
+    R* __restrict__ lout = static_cast<R*>(a.lout);
+    R* __restrict__ gF = static_cast<R*>(a.gF);
+    const uint32_t planeT = uint32_t(PL) * uint32_t(sizeof(T)), planeR = uint32_t(PL) * uint32_t(sizeof(R));
+
+    // Loads of plane xp (and the old dL/dF of plane xp - 2, the plane the
+    // iteration that consumes them writes), issued unconditionally with an
+    // empty range where nothing is wanted.
+    auto issue = [&](int xp, bool wanted) {
+        const bool live = wanted && present(xp);
+        const int px = wrapi(xp, g.nx);
+        const T* bf = ft + (long long)px * PL;
+        const R* bl = lin + (long long)px * PL;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Lf[q] = Buf<T>::ld(make_rsrc(bf, live ? planeT : 0u), loffT);
+            La[q] = Buf<R>::ld(make_rsrc(bl, live ? planeR : 0u), loffR);
+            bf += N;
+            bl += N;
+        }
+        if constexpr (FORCE) {
+            const R* bF = F + (long long)px * PL;
+            const int xo = xp - 2;
+            const bool lo = wanted && gF != nullptr && xo >= s && xo < e && present(xo);
+            const R* bG = gF + (long long)wrapi(xo, g.nx) * PL;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Fl[k] = Buf<R>::ld(make_rsrc(bF, live ? planeR : 0u), loffR);
+                gFl[k] = Buf<R>::ld(make_rsrc(bG, lo ? planeR : 0u), ooffR);
+                bF += N;
+                bG += N;
+            }
+        }
+    };
+
+    if constexpr (WALLS) __syncthreads();  // the wall-term table is complete
+    const int total = (e - s) + 4;
+    issue(s - 2, true);
+    for (int i = 0; i < total; ++i) {
+        const int P = s - 2 + i;
+
+        // ---- S1: plane P enters the two outer exchanges ----
+        R Fc[3], gFo[3], mc[4] = {R(1), R(0), R(0), R(0)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Fc[k] = Fl[k];
+            gFo[k] = gFl[k];
+        }
+        if (present(P) && loads) {
+            R v[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lf[q]);
+            const Moments<R> m = moments<R, FORCE>(v, Fc[0], Fc[1], Fc[2]);
+            mc[0] = m.rho;
+            mc[1] = m.ux;
+            mc[2] = m.uy;
+            mc[3] = m.uz;
+            collide<R, FORCE>(v, omega, Fc[0], Fc[1], Fc[2]);
+            if constexpr (WALLS) moving_wall_out(v, myz | xm(P), WT);
+            R nu[Q];
+            opp_relabel(La, nu);
+            sfor<0, Q>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if constexpr (moves_yz(q)) {
+                    XF[yz_index(q) * NC2 + c] = v[q];
+                    XA[yz_index(q) * NC2 + c] = nu[q];
+                }
+            });
+            oA[0] = v[0];
+            oA[1] = v[1];
+            oA[2] = v[10];
+            oB[0] = nu[0];
+            oB[1] = nu[1];
+            oB[2] = nu[10];
+        }
+        issue(P + 1, i + 1 < total);
+        __syncthreads();
+
+        // ---- S2: plane P-1 on the tile plus one cell: f_{t+1}, lambda_{t+1} ----
+        R gFa[3] = {R(0), R(0), R(0)};
+        if (rad <= 1 && gofs >= 0) {
+            const uint32_t bd = byz | xb(P - 1), bn = byz | xb(P);
+            complete<R, WALLS>(accA, XF, NC2, c, WZ2, oA[1], bd);
+            complete<R, WALLS>(accB, XA, NC2, c, WZ2, oB[1], bd);
+            if (present(P - 1)) {
+                R mu[Q], lam[Q], nu[Q];
+                opp_relabel(accB, mu);
+                collide_adjoint<R, FORCE>(accA, mu, omega, Fh1[0], Fh1[1], Fh1[2], lam, gFa[0], gFa[1], gFa[2]);
+                opp_relabel(lam, nu);
+                sfor<0, Q>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    if constexpr (moves_yz(q)) XC[yz_index(q) * NC1 + ci1] = nu[q];
+                });
+                oC[0] = nu[0];
+                oC[1] = nu[1];
+                oC[2] = nu[10];
+            }
+            deposit<R, WALLS>(accA, nxtA, XF, NC2, c, WZ2, oA[0], oA[1], oA[2], bn);
+            deposit<R, WALLS>(accB, nxtB, XA, NC2, c, WZ2, oB[0], oB[1], oB[2], bn);
+        }
+        __syncthreads();
+
+        // ---- S3: plane P-2 on the tile: lambda_t and dL/dF ----
+        const int po = P - 2;
+        const bool out = po >= s && po < e && present(po);
+        R lam0[Q], go[3];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) lam0[q] = R(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) go[k] = R(0);
+        if (rad == 0 && gofs >= 0) {
+            complete<R, WALLS>(accC, XC, NC1, ci1, WZ1, oC[1], byz | xb(po));
+            if (out) {
+                R mu[Q], gx, gy, gz;
+                opp_relabel(accC, mu);
+                collide_adjoint_m<R, FORCE>(mh2[0], mh2[1], mh2[2], mh2[3], mu, omega, Fh2[0], Fh2[1], Fh2[2], lam0,
+                                            gx, gy, gz);
+                go[0] = gFo[0] + (gFp[0] + gx);
+                go[1] = gFo[1] + (gFp[1] + gy);
+                go[2] = gFo[2] + (gFp[2] + gz);
+            }
+            deposit<R, WALLS>(accC, nxtC, XC, NC1, ci1, WZ1, oC[0], oC[1], oC[2], byz | xb(P - 1));
+        }
+        {
+            const R* bq = lout + (long long)wrapi(po, g.nx) * PL;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                Buf<R>::st(lam0[q], make_rsrc(bq, out ? planeR : 0u), ooffR);
+                bq += N;
+            }
+            if constexpr (FORCE) {
+                const bool og = out && gF != nullptr;
+                const R* bG = gF + (long long)wrapi(po, g.nx) * PL;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Buf<R>::st(go[k], make_rsrc(bG, og ? planeR : 0u), ooffR);
+                    bG += N;
+                }
+            }
+        }
+
+        // ---- histories move one plane ----
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            gFp[k] = gFa[k];
+            Fh2[k] = Fh1[k];
+            Fh1[k] = Fc[k];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            mh2[j] = mh1[j];
+            mh1[j] = mc[j];
+        }
+    }
+}
+
+template <int S, int TY, int TZ, int NT>
+static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, const void* lin, void* lout, void* gF,
+                                 hipStream_t st)
+{
+    Adj2Args a;
+    a.g = g;
+    a.ft = ft;
+    a.F = F;
+    a.lin = lin;
+    a.lout = lout;
+    a.gF = gF;
+    a.nty = (g.ny + TY - 1) / TY;
+    a.ntz = (g.nz + TZ - 1) / TZ;
+    // enough work items to fill the chip twice over, segments of at least 8 planes
+    const int tiles = a.nty * a.ntz;
+    int nseg = (512 + tiles - 1) / tiles;
+    if (nseg > g.nx / 8) nseg = g.nx / 8;
+    if (nseg < 1) nseg = 1;
+    a.seg_len = (g.nx + nseg - 1) / nseg;
+    a.nseg = (g.nx + a.seg_len - 1) / a.seg_len;
+    const dim3 grid(unsigned(tiles * a.nseg));
+    const bool walls = g.wall[0] || g.wall[1] || g.wall[2];
+    const bool force = F != nullptr;
+    if (walls) {
+        if (force)
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, true>), grid, dim3(NT), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, false>), grid, dim3(NT), 0, st, a);
+    } else {
+        if (force)
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, false, true>), grid, dim3(NT), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, false, false>), grid, dim3(NT), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint2(int storage, const Geom& g, const void* f_t, const void* F, const void* lam_in,
+                                void* lam_out, void* grad_force, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return adjoint2_shape<ST_F64, 8, 8, 256>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F32: return adjoint2_shape<ST_F32, 16, 16, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

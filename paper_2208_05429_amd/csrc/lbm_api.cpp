@@ -302,17 +302,23 @@ void timing_end(lbm_ctx* ctx, long idx)
     if (idx >= 0) (void)hipEventRecord(ctx->ev[idx + 1], ctx->stream);
 }
 
-lbm_status march_pass(lbm_ctx* ctx, int M)
+// One marching pass of M steps from src into dst (dst == src: in place).
+lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
 {
     const MarchPlan& p = ctx->plan[M];
     int* flags = reinterpret_cast<int*>(ctx->work + ctx->off_flags);
     void* side = ctx->work + ctx->off_side;
-    lbm_status st = device_err(ctx, launch_prepass(ctx->cfg.storage, ctx->g, p, ctx->f, side, flags, ctx->stream),
-                               "prepass launch");
-    if (st != LBM_OK) return st;
+    const bool inplace = src == dst;
+    if (inplace) {
+        lbm_status st = device_err(ctx, launch_prepass(ctx->cfg.storage, ctx->g, p, src, side, flags, ctx->stream),
+                                   "prepass launch");
+        if (st != LBM_OK) return st;
+    }
     MarchArgs a;
     a.g = ctx->g;
-    a.f = ctx->f;
+    a.f = const_cast<void*>(src);
+    a.fo = dst;
+    a.inplace = inplace ? 1 : 0;
     a.side = side;
     a.force = ctx->force;
     a.flags = flags;
@@ -407,14 +413,50 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n)
         break;
     }
     case LBM_SWAP1:
-        for (int64_t k = 0; k < n && st == LBM_OK; ++k) st = march_pass(ctx, 1);
+        for (int64_t k = 0; k < n && st == LBM_OK; ++k) st = march_pass(ctx, 1, ctx->f, ctx->f);
         break;
     default:
-        for (int64_t k = 0; k < n / 2 && st == LBM_OK; ++k) st = march_pass(ctx, 2);
-        if (st == LBM_OK && (n & 1)) st = march_pass(ctx, 1);
+        for (int64_t k = 0; k < n / 2 && st == LBM_OK; ++k) st = march_pass(ctx, 2, ctx->f, ctx->f);
+        if (st == LBM_OK && (n & 1)) st = march_pass(ctx, 1, ctx->f, ctx->f);
         break;
     }
     return st;
+}
+
+lbm_status lbm_step_into(lbm_ctx* ctx, const void* f_src, void* f_dst, int32_t k)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->err.clear();
+    if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
+    if (!f_src || !f_dst) return fail(&ctx->err, LBM_EINVAL, "f_src and f_dst are required");
+    if (f_src == f_dst) return fail(&ctx->err, LBM_EINVAL, "f_src and f_dst must differ (lbm_step updates in place)");
+    if (!aligned(f_src) || !aligned(f_dst)) return fail(&ctx->err, LBM_EINVAL, "buffers must be 256-byte aligned");
+    const size_t bytes = size_t(19) * size_t(ctx->g.N) * elem_size(ctx->cfg.storage);
+    const char* a0 = static_cast<const char*>(f_src);
+    const char* b0 = static_cast<const char*>(f_dst);
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(&ctx->err, LBM_EINVAL, "f_src and f_dst overlap");
+    switch (ctx->cfg.scheme) {
+    case LBM_TWO_ARRAY: {
+        void* second = ctx->work + ctx->off_second;
+        const bool force = ctx->force != nullptr;
+        if (k == 1)
+            return device_err(ctx, launch_two_array(ctx->cfg.storage, force, ctx->g, f_src, f_dst, ctx->force, ctx->stream),
+                              "two-array step launch");
+        lbm_status st = device_err(
+            ctx, launch_two_array(ctx->cfg.storage, force, ctx->g, f_src, second, ctx->force, ctx->stream),
+            "two-array step launch");
+        if (st != LBM_OK) return st;
+        return device_err(ctx, launch_two_array(ctx->cfg.storage, force, ctx->g, second, f_dst, ctx->force, ctx->stream),
+                          "two-array step launch");
+    }
+    case LBM_SWAP1: {
+        lbm_status st = march_pass(ctx, 1, f_src, f_dst);
+        if (st == LBM_OK && k == 2) st = march_pass(ctx, 1, f_dst, f_dst);
+        return st;
+    }
+    default:
+        return march_pass(ctx, k, f_src, f_dst);
+    }
 }
 
 lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double* unorm_dev, double* sums_host)

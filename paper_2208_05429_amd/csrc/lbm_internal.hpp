@@ -37,12 +37,25 @@ struct MarchPlan {
 
 struct MarchArgs {
     Geom g;
-    void* f;            // distributions, in place
+    void* f;            // distributions read (time t)
+    void* fo;           // distributions written (time t+M): f itself in place, else another buffer
+    int inplace;        // fo == f: side planes and progress counters guard the in-place update
     void* side;         // time-t copies of the first M planes of every segment
     const void* force;  // 3N or null
     int* flags;         // progress (planes loaded) of every work item
     int nty, ntz, nseg, seg_len, ry, rz, xcd_remap;
     int fstride;  // ints between two progress counters (counter of work item w at flags[(1 + w) * fstride])
+};
+
+// One merged two-step adjoint pass (out of place).
+struct Adj2Args {
+    Geom g;
+    const void* ft;    // state f_t (storage type)
+    const void* F;     // 3N force or null
+    const void* lin;   // lambda_{t+2}, 19N of the arithmetic type
+    void* lout;        // lambda_t
+    void* gF;          // 3N force gradient, accumulated (may be null)
+    int nty, ntz, nseg, seg_len;
 };
 
 // Launchers; each returns the hipError_t of its launch.
@@ -60,5 +73,7 @@ hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const vo
                                 const void* grad_u, void* lambda, void* grad_force, hipStream_t s);
 hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, const void* f_t, const void* F,
                                const void* lam_in, void* lam_out, void* grad_force, hipStream_t s);
+hipError_t launch_step_adjoint2(int storage, const Geom& g, const void* f_t, const void* F, const void* lam_in,
+                                void* lam_out, void* grad_force, hipStream_t s);
 
 }  // namespace lbm

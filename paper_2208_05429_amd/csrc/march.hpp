@@ -261,7 +261,8 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         }
     }
 
-    T* __restrict__ f = static_cast<T*>(a.f);
+    const T* __restrict__ f = static_cast<const T*>(a.f);
+    T* __restrict__ fo = static_cast<T*>(a.fo);
     const T* __restrict__ side = static_cast<const T*>(a.side);
     const R* __restrict__ F = static_cast<const R*>(a.force);
 
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     // issue keeps the compiler's count of outstanding memory operations exact.
     auto issue_load_slot = [&](int xp, bool wanted, int k) {
         const bool live = wanted && present(xp);
-        const bool from_side = xp >= e && has_next;
+        const bool from_side = a.inplace && xp >= e && has_next;
         const int px = wrapi(xp, g.nx);
         const T* base;
         long long qstride;
@@ -337,6 +338,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         } else {
             zz = wrapi(zz, a.ntz);
         }
+        if (!a.inplace) fkind = 0;  // out of place: nothing to guard
         if (fkind) flp = a.flags + (1 + ((long long)sg * a.nty + yy) * a.ntz + zz) * a.fstride;
     }
     // plane r is stored in iteration i = r - s + 2M + 1; every work item whose
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     // do not own a finished interior column carry an out-of-range offset and a
     // plane that is not stored this iteration gets an empty range.
     auto store = [&](const R (&out)[Q], int k, int r, bool live) {
-        const T* bq = f + (long long)(live ? r : 0) * PL;
+        const T* bq = fo + (long long)(live ? r : 0) * PL;
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {

@@ -336,7 +336,8 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             Lg[b][q] = T(0);
         }
 
-    T* __restrict__ f = static_cast<T*>(a.f);
+    const T* __restrict__ f = static_cast<const T*>(a.f);
+    T* __restrict__ fo = static_cast<T*>(a.fo);
     const T* __restrict__ side = static_cast<const T*>(a.side);
     const R* __restrict__ F = static_cast<const R*>(a.force);
     const uint32_t plane_bytes = uint32_t(PL) * uint32_t(sizeof(T));
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     // plane is absent or past the end), so the outstanding-operation counts
     // the compiler tracks stay exact.
     auto plane_base = [&](int xp, long long& qstride) -> const T* {
-        if (xp >= e && has_next) {
+        if (a.inplace && xp >= e && has_next) {
             qstride = PL;
             return side + ((long long)(nseg_next * M + (xp - e)) * Q) * PL;
         }
@@ -418,6 +419,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         } else {
             zz = wrapi(zz, a.ntz);
         }
+        if (!a.inplace) fkind = 0;  // out of place: nothing to guard
         if (fkind) flp = a.flags + (1 + ((long long)sg * a.nty + yy) * a.ntz + zz) * a.fstride;
     }
     // plane r is stored in iteration i = r - s + 2M; a work item whose halo
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     };
 
     auto store_pair = [&](const R (&v0)[Q], const R (&v1)[Q], int r, bool live) {
-        const T* bq = f + (long long)(live ? r : 0) * PL;
+        const T* bq = fo + (long long)(live ? r : 0) * PL;
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {

@@ -82,6 +82,11 @@ class Lattice:
         capi.lbm_set_stream(self.ctx, _stream_handle())
         capi.lbm_step(self.ctx, n)
 
+    def step_into(self, src, dst, k: int):
+        """k in {1, 2} steps from state tensor src into dst (out of place; self.f untouched)."""
+        capi.lbm_set_stream(self.ctx, _stream_handle())
+        capi.lbm_step_into(self.ctx, _ptr(src), _ptr(dst), k)
+
     def macroscopic(self, sums=False, want=("rho", "u", "unorm")):
         capi.lbm_set_stream(self.ctx, _stream_handle())
         rho = torch.empty(self.shape, dtype=torch.float64, device=self.device) if "rho" in want else None

@@ -72,6 +72,7 @@ def test_null_and_state_errors():
                     ctypes.byref(out))
     assert st == capi.LBM_EINVAL
     assert L.lbm_step(None, 1) == capi.LBM_ESTATE
+    assert L.lbm_step_into(None, None, None, 2) == capi.LBM_ESTATE
     assert L.lbm_macroscopic(None, None, None, None, None) == capi.LBM_ESTATE
     assert L.lbm_step_adjoint(None, None, None, None, None, 1) == capi.LBM_ESTATE
     assert L.lbm_set_stream(None, None) == capi.LBM_ESTATE

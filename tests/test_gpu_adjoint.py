@@ -115,3 +115,74 @@ def test_force_gradient_matches_central_differences_fp64():
             d1, d2 = fd(x, y, z, a, 1e-4), fd(x, y, z, a, 5e-5)
             assert abs(d1 - g[a, x, y, z]) <= 2e-4 * gmax, (x, y, z, a)
             assert abs((4 * d2 - d1) / 3 - g[a, x, y, z]) <= 1e-6 * gmax, (x, y, z, a)
+
+
+# Two merged reverse steps (one pass, f_{t+1} recomputed on chip) against two
+# single reverse steps of the oracle.  Shapes span several 16x16 (FP32) or 8x8
+# (FP64) tiles with ragged last tiles and several x segments.
+MERGED_CASES = [
+    ((40, 21, 19), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
+    ((24, 18, 37), (PERIODIC,) * 6, (0.0, 0.0, 0.0), True),
+    ((17, 20, 22), (WALL, WALL, WALL, 2, WALL, WALL), (0.04, 0.0, -0.01), True),
+    ((19, 13, 26), (2, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.03, 0.02), False),
+]
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+@pytest.mark.parametrize("case", range(len(MERGED_CASES)))
+def test_merged_adjoint_matches_two_single_steps(storage, tol, case):
+    shape, faces, wall_u, with_force = MERGED_CASES[case]
+    names = [{PERIODIC: "periodic", WALL: "wall", 2: "moving"}[f] for f in faces]
+    print(f"[gpu] merged adjoint {storage} {shape} {names} force={with_force}", flush=True)
+    rho0, u0 = _init(shape, 31 + case)
+    F = wl.normal_field(shape, 1e-4, 32 + case) if with_force else None
+    o = Oracle(shape, 0.7, faces=faces, wall_u=wall_u)
+    f_t = o.run(o.init(rho0, u0), 2, F)
+    f_t1 = o.run(f_t, 1, F)
+    lam2 = wl.normal_field(shape, 1.0, 33 + case, comps=19)
+    lam1, g1 = o.adjoint_step(f_t1, lam2, F)
+    lam0, g0 = o.adjoint_step(f_t, lam1, F, g1)
+
+    rdt = real_dtype(storage)
+    force = None if F is None else torch.as_tensor(F)
+    lat = Lattice(shape, 0.7, storage, "swap2", names, wall_u, force=force, rho0=torch.as_tensor(rho0),
+                  u0=torch.as_tensor(u0))
+    lat.step(2)
+    lin = torch.as_tensor(lam2, dtype=rdt, device="cuda").contiguous()
+    lout = torch.empty_like(lin)
+    gF = torch.zeros((3,) + shape, dtype=rdt, device="cuda")
+    gptr = gF.data_ptr() if F is not None else None
+    capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), lout.data_ptr(), gptr, 2)
+    torch.cuda.synchronize()
+    e = np.abs(lout.double().cpu().numpy() - lam0).max() / np.abs(lam0).max()
+    assert e <= 10 * tol, e
+    if F is not None:
+        eg = np.abs(gF.double().cpu().numpy() - g0).max() / np.abs(g0).max()
+        assert eg <= 10 * tol, eg
+    # and against two single-step launches of the library itself
+    f1 = lat.f.clone()
+    lat.step(1)
+    mid = torch.empty_like(lin)
+    g2 = torch.zeros_like(gF)
+    gptr2 = g2.data_ptr() if F is not None else None
+    capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), mid.data_ptr(), gptr2, 1)
+    lout1 = torch.empty_like(lin)
+    capi.lbm_step_adjoint(lat.ctx, f1.data_ptr(), mid.data_ptr(), lout1.data_ptr(), gptr2, 1)
+    torch.cuda.synchronize()
+    e2 = (lout1.double() - lout.double()).abs().max().item() / lout1.double().abs().max().item()
+    assert e2 <= 10 * tol, e2
+    lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_force_gradient_merged_matches_oracle_adjoint(storage):
+    shape, steps = (16, 12, 10), 12
+    o, f0, F, ut, f0_dev = _channel_problem(shape, steps, storage)
+    L_ref, g_ref = o.loss_and_grad(f0, F, ut, steps)
+    for ck in (4, 5):  # even and odd checkpoint segments (odd ones end with one single reverse step)
+        spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=ck, merged=True)
+        L, g = force_gradient(torch.as_tensor(F, device="cuda"), f0_dev, spec, torch.as_tensor(ut, device="cuda"))
+        g = g.double().cpu().numpy()
+        err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+        print(f"{storage} checkpoint {ck}: merged-adjoint gradient error vs oracle adjoint {err:.3e}")
+        assert err <= (1e-10 if storage == "f64" else 1e-3)

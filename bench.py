@@ -27,7 +27,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-METRIC = "D3Q19 MLUPS (single-copy, two-step merged, % HBM roofline), 1 GPU"
+METRIC = "D3Q19 MLUPS and % HBM roofline, 1 GPU; adjoint/forward step-time ratio"
 
 
 def parse():
@@ -41,8 +41,10 @@ def parse():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="also run one device-to-device copy of BYTES bytes (counter calibration)")
+    ap.add_argument("--copy-probe", type=int, default=1 << 31, metavar="BYTES",
+                    help="device-to-device copy of BYTES bytes: achievable read+write rate, counter calibration")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--no-storage-sweep", action="store_true", help="skip the FP16/BF16 storage runs")
     return ap.parse_args()
 
 
@@ -89,6 +91,103 @@ def cpu_baseline(target_s):
     n = int(np.prod(shape))
     return {"value": round(n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"64^3 periodic Taylor-Green+noise, tau=0.6, {steps} steps, FP64 two-array, {el:.1f} s"}
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def adjoint_ratio(shape, steps, checkpoint, reps=3):
+    """Backward (recompute + merged adjoint) time per step over merged forward
+    time per step, for L = sum |u_T - u*|^2 on a channel (periodic x, walls in
+    y and z, tau 0.8) under a per-cell force N(0, 1e-12) (seed 1); u* from a
+    forward run under a hidden force (seed 2)."""
+    import torch
+    from paper_2208_05429_amd import workloads as wl
+    from paper_2208_05429_amd.adjoint import ForceAdjoint
+    from paper_2208_05429_amd.lattice import Lattice
+    faces = ("periodic", "periodic", "wall", "wall", "wall", "wall")
+    F = torch.from_numpy(wl.normal_field(shape, 1e-6, 1)).float().cuda()
+    hidden = torch.from_numpy(wl.normal_field(shape, 1e-6, 2)).float().cuda()
+    lat = Lattice(shape, 0.8, "f32", "swap2", faces, force=hidden)
+    f0 = lat.f.clone()
+    lat.step(steps)
+    _, ut, _, _ = lat.macroscopic(want=("u",))
+    lat.close()
+    lat = Lattice(shape, 0.8, "f32", "swap2", faces, force=F, f=f0.clone())
+    spec = dict(shape=shape, tau=0.8, storage="f32", faces=faces, steps=steps, checkpoint=checkpoint, merged=True)
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        lat.f.copy_(f0)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        lat.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        Fp = F.clone().requires_grad_(True)
+        u = ForceAdjoint.apply(Fp, f0, spec)
+        L = ((u - ut.float()) ** 2).sum()
+        torch.cuda.synchronize()
+        b0, b1 = _events()
+        b0.record()
+        L.backward()
+        b1.record()
+        torch.cuda.synchronize()
+        if r:  # the first round warms up
+            fwd.append(e0.elapsed_time(e1))
+            bwd.append(b0.elapsed_time(b1))
+    # the adjoint kernel alone, one merged reverse pass, against one merged forward pass
+    lam = torch.randn((19,) + tuple(shape), device="cuda")
+    lout = torch.empty_like(lam)
+    gF = torch.zeros((3,) + tuple(shape), device="cuda")
+    from paper_2208_05429_amd import capi
+    n = 20
+    a0, a1 = _events()
+    a0.record()
+    for _ in range(n):
+        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lam.data_ptr(), lout.data_ptr(), gF.data_ptr(), 2)
+    a1.record()
+    f1 = torch.empty_like(lat.f)
+    m0, m1 = _events()
+    m0.record()
+    for _ in range(n):
+        lat.step_into(lat.f, f1, 2)
+    m1.record()
+    torch.cuda.synchronize()
+    lat.close()
+    fw, bw = float(np.median(fwd)) / steps, float(np.median(bwd)) / steps
+    ka, kf = a0.elapsed_time(a1) / (2 * n), m0.elapsed_time(m1) / (2 * n)
+    return {"shape": list(shape), "steps": steps, "checkpoint": checkpoint, "forward_ms_per_step": round(fw, 5),
+            "backward_ms_per_step": round(bw, 5), "ratio": round(bw / fw, 3),
+            "adjoint_kernel_ms_per_step": round(ka, 5), "forward_kernel_ms_per_step": round(kf, 5),
+            "kernel_ratio": round(ka / kf, 3)}
+
+
+def storage_sweep(size, steps):
+    """MLUPS of the merged kernel with FP16 / BF16 offset storage on the bench workload."""
+    import torch
+    from paper_2208_05429_amd import workloads as wl
+    from paper_2208_05429_amd.lattice import Lattice
+    shape = (size,) * 3
+    _, u0 = wl.tgv_512_fields(shape)
+    u0 = torch.from_numpy(u0).cuda()
+    out = {}
+    for st in ("f16", "bf16"):
+        lat = Lattice(shape, wl.TGV_512["tau"], st, "swap2", u0=u0)
+        lat.step(4)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        lat.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        out[st] = round(np.prod(shape) * steps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -168,19 +267,37 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "conservation": {"mass": sums[0], "momentum": list(sums[1:])},
     }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
     if a.copy_probe:
+        # the achievable rate of a plain device copy (same 1:1 read/write mix)
         src = torch.empty(a.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record(stream)
         dst.copy_(src)
-        c1.record(stream)
         torch.cuda.synchronize()
-        cms = c0.elapsed_time(c1)
-        out["copy_probe"] = {"bytes": a.copy_probe, "ms": round(cms, 4),
-                             "GB/s (read+write)": round(2 * a.copy_probe / (cms * 1e-3) / 1e9, 1)}
+        best = 1e30
+        for _ in range(3):
+            c0, c1 = _events()
+            c0.record(stream)
+            dst.copy_(src)
+            c1.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, c0.elapsed_time(c1))
+        copy_gbs = 2 * a.copy_probe / (best * 1e-3) / 1e9
+        out["roofline"]["copy_gbs"] = round(copy_gbs, 1)
+        out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        out["copy_probe"] = {"bytes": a.copy_probe, "ms": round(best, 4)}
         del src, dst
+        torch.cuda.empty_cache()
+    if a.storage == "f32" and a.scheme == "swap2" and not a.no_storage_sweep:
+        print("[bench] FP16/BF16 storage runs", file=sys.stderr, flush=True)
+        sw = storage_sweep(a.size, 40)
+        out["reduced_precision"] = {"MLUPS": sw, "speedup_vs_f32": {k: round(v / mlups, 3) for k, v in sw.items()}}
+    if not a.no_adjoint:
+        print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
+        out["adjoint"] = {"workload": adjoint_ratio((128, 64, 64), 200, 20),
+                          "bandwidth_bound": adjoint_ratio((256, 256, 256), 40, 20, reps=2)}
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)

@@ -187,17 +187,29 @@ __device__ __forceinline__ void wall_terms_to(R* tab, int lane, R uwx, R uwy, R 
 // right after the collision is therefore the same single addition as adding
 // it on receipt.  rmask: receiving directions q of this cell whose source lies
 // beyond the moving face (bit q set: the cell's outgoing opp(q) gets term q).
-// The table is read through a volatile pointer so the Q terms are loaded
-// where they are used, on the few boundary lanes, instead of being kept live
-// across the whole march.
+// The populations that move in y or z are amended in the cell's own exchange
+// slots (X[yz_index(q) * stride + slot], just written by this thread), the two
+// x-only ones (q = 1, 10) in registers; nothing extra stays live.  The term
+// table is read through a volatile pointer so the terms are loaded where they
+// are used, on the few lanes next to the moving face.
 template <class R>
-__device__ __forceinline__ void moving_wall_out(R (&v)[Q], uint32_t rmask, const R* tab)
+__device__ __forceinline__ void moving_wall_out(R& v1, R& v10, R* X, int stride, int slot, uint32_t rmask,
+                                                const R* tab)
 {
-    if (rmask == 0u) return;
+    if (!__any(rmask != 0u)) return;  // wave-uniform: waves away from the moving face skip it
     const volatile R* t = tab;
     sfor<1, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        if ((rmask >> q) & 1u) v[oppq(q)] += t[q];
+        constexpr int qo = oppq(q);
+        const bool hit = (rmask >> q) & 1u;
+        if constexpr (moves_yz(qo)) {
+            const R x = X[yz_index(qo) * stride + slot];
+            X[yz_index(qo) * stride + slot] = hit ? x + t[q] : x;
+        } else if constexpr (qo == 1) {
+            v1 = hit ? v1 + t[q] : v1;
+        } else {
+            v10 = hit ? v10 + t[q] : v10;
+        }
     });
 }
 

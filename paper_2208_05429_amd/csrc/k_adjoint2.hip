@@ -210,7 +210,6 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
             mc[2] = m.uy;
             mc[3] = m.uz;
             collide<R, FORCE>(v, omega, Fc[0], Fc[1], Fc[2]);
-            if constexpr (WALLS) moving_wall_out(v, myz | xm(P), WT);
             R nu[Q];
             opp_relabel(La, nu);
             sfor<0, Q>([&](auto qc) {
@@ -220,6 +219,7 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
                     XA[yz_index(q) * NC2 + c] = nu[q];
                 }
             });
+            if constexpr (WALLS) moving_wall_out(v[1], v[10], XF, NC2, c, myz | xm(P), WT);
             oA[0] = v[0];
             oA[1] = v[1];
             oA[2] = v[10];

@@ -419,12 +419,12 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 #pragma unroll
                 for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
                 collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
-                if constexpr (WALLS) moving_wall_out(v, myz[k] | xmc, WT);
                 const int c = tid + k * NT;
                 sfor<0, Q>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
                     if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + c] = v[q];
                 });
+                if constexpr (WALLS) moving_wall_out(v[1], v[10], X1w, NC, c, myz[k] | xmc, WT);
                 o1[k][0] = v[0];
                 o1[k][1] = v[1];
                 o1[k][2] = v[10];
@@ -477,11 +477,12 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     complete<R, WALLS>(acc1[k], X1w, NC, c, WZ, o1[k][1], byz[k] | xbd1);
                     if (coll2) {
                         collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
-                        if constexpr (WALLS) moving_wall_out(acc1[k], myz[k] | xmc2, WT);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
                             if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = acc1[k][q];
                         });
+                        if constexpr (WALLS)
+                            moving_wall_out(acc1[k][1], acc1[k][10], X2, NC2, ci2[k], myz[k] | xmc2, WT);
                         o2[k][0] = acc1[k][0];
                         o2[k][1] = acc1[k][1];
                         o2[k][2] = acc1[k][10];

@@ -96,64 +96,131 @@ __device__ __forceinline__ int split_at(int c, int d)
 }
 
 // complete() / deposit() of march.hpp on a parity-split buffer of 16 rows of
-// STRIDE columns with row pitch WZL.
+// STRIDE columns with row pitch WZL, with walls handled through ghost slots.
+//
+// Walls in y and z.  A population whose source lies beyond a y/z wall is the
+// receiving cell's own reversed post-collision value (plus the moving-wall
+// term).  The receiver itself writes that value into the exchange slot it is
+// about to pull from: the slot of an out-of-domain position, which no other
+// cell reads or writes.  The pulls are then the periodic ones, unchanged:
+//   c_x = 0   ghost written right after the collision (ghost_out);
+//   c_x = +1  the pending value in nxt[] is replaced right after the
+//             collision (ghost_out);
+//   c_x = -1  pulled one iteration later from the next plane's exchange:
+//             ghost written at deposit time, into the buffer that plane will
+//             use (Xg), where it survives because collisions write only slots
+//             of cells inside the domain.
+// Lanes without such a link write to a sink at the end of the buffer
+// instead of branching.
+// Walls in x are uniform over a plane (xw: the receiving directions of this
+// plane whose source plane is beyond an x wall): deposit puts the reversed
+// values in place and complete keeps them.
+// A copy of v the compiler cannot see through: keeps a computation that
+// depends on it inside the loop instead of hoisted (and kept live) outside.
+__device__ __forceinline__ int opaque(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
-__device__ __forceinline__ void complete_s(R (&acc)[Q], const R* __restrict__ X, int ci, R o1, uint32_t bdone)
+__device__ __forceinline__ void complete_s(R (&acc)[Q], const R* __restrict__ X, int ci, R o1, uint32_t xw)
 {
     constexpr int HALF = STRIDE / 2;
+    // next to an x wall (uniform over the plane) every c_x = -1 population was
+    // put in place by deposit_s, and there is nothing to receive
+    if (WALLS && (xw & mask_cx(-1)) != 0u) return;
     sfor<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         if constexpr (cxq(q) == -1) {
-            R rv;
             if constexpr (moves_yz(q))
-                rv = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
+                acc[q] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
             else
-                rv = o1;
-            if constexpr (WALLS)
-                acc[q] = ((bdone >> q) & 1u) ? acc[q] : rv;
-            else
-                acc[q] = rv;
+                acc[q] = o1;
         }
     });
 }
 
+// own reversed post-collision value of direction q (its opposite's slot)
+template <class R, int PAR, int STRIDE, int q>
+__device__ __forceinline__ R own_reversed(const R* __restrict__ X, int ci, R o1, R o10)
+{
+    constexpr int qo = oppq(q);
+    if constexpr (moves_yz(qo))
+        return X[yz_index(qo) * STRIDE + split_at<PAR, STRIDE / 2>(ci, 0)];
+    else
+        return (qo == 1) ? o1 : o10;
+}
+
 template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
-__device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], const R* __restrict__ X, int ci, R o0, R o1,
-                                          R o10, uint32_t bnext)
+__device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], R* __restrict__ X, int ci, R o0, R o1, R o10,
+                                          uint32_t xw, uint32_t byz, uint32_t mv, const R* WT, R* Xg, int lane)
 {
     constexpr int HALF = STRIDE / 2;
     sfor<0, Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        constexpr int qo = oppq(q);
-        R bval = R(0);
-        if constexpr (WALLS && q != 0) {
-            if constexpr (moves_yz(qo))
-                bval = X[yz_index(qo) * STRIDE + split_at<PAR, HALF>(ci, 0)];
-            else
-                bval = (qo == 1) ? o1 : o10;
-        }
         if constexpr (cxq(q) == 0) {
-            R rv;
             if constexpr (q == 0)
-                rv = o0;
+                acc[q] = o0;
             else
-                rv = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
-            if constexpr (WALLS && q != 0)
-                acc[q] = ((bnext >> q) & 1u) ? bval : rv;
-            else
-                acc[q] = rv;
+                acc[q] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
         } else if constexpr (cxq(q) == 1) {
             constexpr int j = xp_index(q);
-            if constexpr (WALLS)
-                acc[q] = ((bnext >> q) & 1u) ? bval : nxt[j];
-            else
-                acc[q] = nxt[j];
+            acc[q] = nxt[j];
             if constexpr (moves_yz(q))
                 nxt[j] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
             else
                 nxt[j] = o10;
-        } else {
-            if constexpr (WALLS) acc[q] = bval;
+        }
+    });
+    if constexpr (WALLS) {
+        if (xw != 0u) {  // a plane next to an x wall (uniform)
+            const int cio = opaque(ci);
+            sfor<1, Q>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if constexpr (cxq(q) != 0) {
+                    if ((xw >> q) & 1u) {
+                        const R own = own_reversed<R, PAR, STRIDE, q>(X, cio, o1, o10);
+                        acc[q] = ((mv >> q) & 1u) ? own + WT[opaque(q)] : own;
+                    }
+                }
+            });
+        }
+        if (__any(byz != 0u)) {  // c_x = -1 ghosts for the next plane's completion
+            const int cio = opaque(ci), sk = opaque(16 * STRIDE + lane);
+            sfor<1, Q>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if constexpr (cxq(q) == -1 && moves_yz(q)) {
+                    const bool hit = (byz >> q) & 1u;
+                    const R own = own_reversed<R, PAR, STRIDE, q>(X, cio, o1, o10);
+                    const int gi = yz_index(q) * STRIDE + split_at<PAR, HALF>(cio, -cyq(q) * WZL - czq(q));
+                    Xg[hit ? gi : sk] = ((mv >> q) & 1u) ? own + WT[opaque(q)] : own;
+                }
+            });
+        }
+    }
+}
+
+// Right after a receiving cell's collision (v: its post-collision values,
+// already written to its own slots): c_x = 0 ghosts and c_x = +1 replacements.
+template <class R, int PAR, int STRIDE, int WZL>
+__device__ __forceinline__ void ghost_out(const R (&v)[Q], R (&nxt)[5], R* __restrict__ X, int ci, uint32_t byz,
+                                          uint32_t myz, const R* WT, int lane)
+{
+    constexpr int HALF = STRIDE / 2;
+    if (!__any(byz != 0u)) return;
+    const int cio = opaque(ci), sk = opaque(16 * STRIDE + lane);
+    sfor<1, Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (moves_yz(q) && cxq(q) >= 0) {
+            const bool hit = (byz >> q) & 1u;
+            const R val = ((myz >> q) & 1u) ? v[oppq(q)] + WT[opaque(q)] : v[oppq(q)];
+            if constexpr (cxq(q) == 0) {
+                const int gi = yz_index(q) * STRIDE + split_at<PAR, HALF>(cio, -cyq(q) * WZL - czq(q));
+                X[hit ? gi : sk] = val;
+            } else {
+                nxt[xp_index(q)] = hit ? val : nxt[xp_index(q)];
+            }
         }
     });
 }
@@ -202,8 +269,9 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     static_assert(sizeof(T) == 2 || sizeof(T) == 4, "32-bit arithmetic storages");
     static_assert(PF == 1 || PF == 2, "loads run one or two planes ahead");
 
-    __shared__ R X1[NB1][16 * NC];
-    __shared__ R X2[(M == 2) ? 16 * NC2 : 1];
+    constexpr int SK = WALLS ? 64 : 0;  // each exchange buffer ends in a sink for ghost writes of lanes without a wall link
+    __shared__ R X1[NB1][16 * NC + SK];
+    __shared__ R X2[(M == 2) ? 16 * NC2 + SK : 1];
     __shared__ R WT[WALLS ? Q : 1];  // moving-wall terms (entry q: received along c_q)
 
     const Geom& g = a.g;
@@ -221,12 +289,27 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
     const R omega = R(g.omega);
     if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+    // receiving directions whose source lies beyond the moving face, for a
+    // cell next to it (y or z face; an x face is handled per plane by xm)
+    uint32_t mface = 0u;
+    if constexpr (WALLS) {
+        sfor<1, Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int f = g.moving_face;
+            if ((f == 2 && cyq(q) == 1) || (f == 3 && cyq(q) == -1) || (f == 4 && czq(q) == 1) ||
+                (f == 5 && czq(q) == -1))
+                mface |= 1u << q;
+        });
+    }
+    // moving-wall links of a column (its bounce mask with the bit-31 flag)
+    auto mlinks = [&](uint32_t b) -> uint32_t { return (b >> 31) ? (b & mface) : 0u; };
+    const int lane = tid & 63;
     const long long N = g.N, PL = g.PL;
 
     // ---- the three columns of this thread: 0, 1 = interior pair, 2 = ring ----
     constexpr int K = 3;
     int gofs[K], rad[K], ci[K], ci2[K];
-    uint32_t voff[K], byz[K], myz[K];
+    uint32_t voff[K], byz[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         gofs[k] = -1;
@@ -235,7 +318,6 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         ci2[k] = 0;
         voff[k] = kOffNone;
         byz[k] = 0;
-        myz[k] = 0;
         int ly = 0, lz = 0;
         bool have = true;
         if (k < 2) {
@@ -277,8 +359,9 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                     if (g.moving_face >= 0 && (f1 == g.moving_face || f2 == g.moving_face)) mv |= 1u << q;
                 }
             });
-            byz[k] = b;
-            myz[k] = mv;
+            // bit 31: the column touches the moving face; its moving-wall links
+            // are then exactly byz & mface (mface below, uniform)
+            byz[k] = b | (mv ? 0x80000000u : 0u);
         }
     }
     // memory offsets: the pair moves as one access keyed on its first column
@@ -451,7 +534,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     };
 
     // step-1 collide of column k from its raw values (decoded here)
-    auto collide1 = [&](auto kc, R* X1w, const P2 (&LP)[Q], const T (&LG)[Q], const R (&Fb)[K][3], uint32_t mwall) {
+    auto collide1 = [&](auto kc, R* X1w, const P2 (&LP)[Q], const T (&LG)[Q], const R (&Fb)[K][3]) {
         constexpr int k = decltype(kc)::value;
         R v[Q];
 #pragma unroll
@@ -462,12 +545,16 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 v[q] = Cd::dec(LG[q]);
         }
         collide<R, FORCE>(v, omega, Fb[k][0], Fb[k][1], Fb[k][2]);
-        if constexpr (WALLS) moving_wall_out(v, mwall, WT);
         const int sl = ((ci[k] & 1) ? NC / 2 : 0) + (ci[k] >> 1);
         sfor<0, Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + sl] = v[q];
         });
+        if constexpr (WALLS) {
+            // level-1 receivers: the tile plus M-1 halo cells
+            constexpr int PARk = (k == 0) ? (M & 1) : ((k == 1) ? ((M + 1) & 1) : -1);
+            if (rad[k] <= M - 1) ghost_out<R, PARk, NC, WZ>(v, nxt1[k], X1w, ci[k], byz[k], mlinks(byz[k]), WT, lane);
+        }
         o1[k][0] = v[0];
         o1[k][1] = v[1];
         o1[k][2] = v[10];
@@ -485,6 +572,14 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     auto iteration = [&](auto pbc, int i) {
         constexpr int pb = decltype(pbc)::value;
         const int xl = s - M + i;
+        if constexpr (WALLS) {
+            // The wall masks are loop-invariant; left visible, the compiler
+            // hoists every per-direction condition and ghost address out of
+            // the march and runs out of registers.  Recomputing them per plane
+            // costs a few instructions on the few lanes that need them.
+#pragma unroll
+            for (int k = 0; k < K; ++k) asm volatile("" : "+v"(byz[k]));
+        }
         R* X1w = X1[(M == 1) ? (i & 1) : 0];
         const int r_out = xl - M;
         const bool storing = r_out >= s && r_out < e;
@@ -500,42 +595,44 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[pb][k][c];
         }
         const bool pres = present(xl);
-        const uint32_t xmc = xm(xl);
         if (pres && rad[0] <= M && gofs[0] >= 0)
-            collide1(std::integral_constant<int, 0>{}, X1w, Lp[pb], Lg[pb], Fl1[pb], myz[0] | xmc);
+            collide1(std::integral_constant<int, 0>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
         if (pres && rad[1] <= M && gofs[1] >= 0)
-            collide1(std::integral_constant<int, 1>{}, X1w, Lp[pb], Lg[pb], Fl1[pb], myz[1] | xmc);
+            collide1(std::integral_constant<int, 1>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
         load_pair(xl + PF, next_wanted, Lp[pb], Fl1[pb]);
         if (pres && rad[2] <= M && gofs[2] >= 0)
-            collide1(std::integral_constant<int, 2>{}, X1w, Lp[pb], Lg[pb], Fl1[pb], myz[2] | xmc);
+            collide1(std::integral_constant<int, 2>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
         load_ring(xl + PF, next_wanted, Lg[pb], Fl1[pb]);
         __syncthreads();
         if (tid == 0) __hip_atomic_store(a.flags + (1 + (long long)wid) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
-            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmc2 = xm(xl - 1);
+            const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmn1 = xm(xl);
             const bool coll2 = i >= M && present(xl - 1);
             sfor<0, K>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 constexpr int PAR = (k == 0) ? (M & 1) : ((k == 1) ? ((M + 1) & 1) : -1);  // parity of ci
                 constexpr int PAR2 = (k == 0) ? 1 : ((k == 1) ? 0 : -1);                 // parity of ci2
                 if (rad[k] <= 1 && gofs[k] >= 0) {
-                    complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], byz[k] | xbd1);
+                    complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], xbd1);
                     if (coll2) {
                         collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
-                        if constexpr (WALLS) moving_wall_out(acc1[k], myz[k] | xmc2, WT);
                         const int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
                             if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + sl2] = acc1[k][q];
                         });
+                        if constexpr (WALLS && k < 2) {  // level-2 receivers: the tile
+                            if (rad[k] == 0)
+                                ghost_out<R, PAR2, NC2, WZ2>(acc1[k], nxt2[k], X2, ci2[k], byz[k], mlinks(byz[k]), WT, lane);
+                        }
                         o2[k][0] = acc1[k][0];
                         o2[k][1] = acc1[k][1];
                         o2[k][2] = acc1[k][10];
                     }
                     deposit_s<R, WALLS, PAR, NC, WZ>(acc1[k], nxt1[k], X1w, ci[k], o1[k][0], o1[k][1], o1[k][2],
-                                                     byz[k] | xbn1);
+                                                     xbn1, byz[k], mlinks(byz[k]) | xmn1, WT, X1w, lane);
                 }
                 if constexpr (FORCE) {
 #pragma unroll
@@ -548,33 +645,34 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         // ---- D: last-step receive of the pair, hazard check, in-place store ----
         {
             const int p = xl - M + 1;  // plane the last step collided
-            const uint32_t xbd = xb(p - 1), xbn = xb(p);
+            const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
             const bool act = rad[0] == 0 && gofs[0] >= 0;
             if constexpr (M == 2) {
                 if (act) {
-                    complete_s<R, WALLS, 1, NC2, WZ2>(acc2[0], X2, ci2[0], o2[0][1], byz[0] | xbd);
-                    complete_s<R, WALLS, 0, NC2, WZ2>(acc2[1], X2, ci2[1], o2[1][1], byz[1] | xbd);
+                    complete_s<R, WALLS, 1, NC2, WZ2>(acc2[0], X2, ci2[0], o2[0][1], xbd);
+                    complete_s<R, WALLS, 0, NC2, WZ2>(acc2[1], X2, ci2[1], o2[1][1], xbd);
                 }
                 if (storing) poll_finish(seen, i, r_out);
                 store_pair(acc2[0], acc2[1], r_out, storing);
                 if (act) {
                     deposit_s<R, WALLS, 1, NC2, WZ2>(acc2[0], nxt2[0], X2, ci2[0], o2[0][0], o2[0][1], o2[0][2],
-                                                     byz[0] | xbn);
+                                                     xbn, byz[0], mlinks(byz[0]) | xmn, WT, X2, lane);
                     deposit_s<R, WALLS, 0, NC2, WZ2>(acc2[1], nxt2[1], X2, ci2[1], o2[1][0], o2[1][1], o2[1][2],
-                                                     byz[1] | xbn);
+                                                     xbn, byz[1], mlinks(byz[1]) | xmn, WT, X2, lane);
                 }
             } else {
                 if (act) {
-                    complete_s<R, WALLS, 1, NC, WZ>(acc1[0], X1w, ci[0], o1[0][1], byz[0] | xbd);
-                    complete_s<R, WALLS, 0, NC, WZ>(acc1[1], X1w, ci[1], o1[1][1], byz[1] | xbd);
+                    complete_s<R, WALLS, 1, NC, WZ>(acc1[0], X1w, ci[0], o1[0][1], xbd);
+                    complete_s<R, WALLS, 0, NC, WZ>(acc1[1], X1w, ci[1], o1[1][1], xbd);
                 }
                 if (storing) poll_finish(seen, i, r_out);
                 store_pair(acc1[0], acc1[1], r_out, storing);
                 if (act) {
+                    R* X1n = X1[(M == 1) ? ((i + 1) & 1) : 0];  // the buffer the next plane uses
                     deposit_s<R, WALLS, 1, NC, WZ>(acc1[0], nxt1[0], X1w, ci[0], o1[0][0], o1[0][1], o1[0][2],
-                                                   byz[0] | xbn);
+                                                   xbn, byz[0], mlinks(byz[0]) | xmn, WT, X1n, lane);
                     deposit_s<R, WALLS, 0, NC, WZ>(acc1[1], nxt1[1], X1w, ci[1], o1[1][0], o1[1][1], o1[1][2],
-                                                   byz[1] | xbn);
+                                                   xbn, byz[1], mlinks(byz[1]) | xmn, WT, X1n, lane);
                 }
             }
         }

@@ -45,6 +45,7 @@ def parse():
                     help="device-to-device copy of BYTES bytes: achievable read+write rate, counter calibration")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-storage-sweep", action="store_true", help="skip the FP16/BF16 storage runs")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 single-copy run")
     return ap.parse_args()
 
 
@@ -190,6 +191,41 @@ def storage_sweep(size, steps):
     return out
 
 
+def large_run(size, steps):
+    """The large single-copy run: size^3 FP32, periodic, tau 0.55, random-phase
+    Taylor-Green field (seed 4), merged passes in rounds over bands of tile
+    rows when the plane has more tiles than co-resident workgroups."""
+    import torch
+    from paper_2208_05429_amd import workloads as wl
+    from paper_2208_05429_amd.lattice import Lattice
+    cfg = wl.TGV_1024
+    shape = (size,) * 3
+    u0 = wl.taylor_green_3d_device(shape, cfg["u0"], wl.random_phases(cfg["phase_seed"]), "cuda")
+    lat = Lattice(shape, cfg["tau"], "f32", "swap2", u0=u0)
+    del u0
+    torch.cuda.empty_cache()
+    lat.step(2)
+    torch.cuda.synchronize()
+    lat.set_kernel_timing(True)
+    e0, e1 = _events()
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kms, kn = lat.kernel_time()
+    s = lat.sums()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    N = size ** 3
+    kper = kms[1] / max(kn[1], 1)
+    return {"shape": list(shape), "steps": steps, "MLUPS": round(N * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms / steps, 4), "march_ms_per_pass": round(kper, 4),
+            "achieved_GBs": round(2 * 19 * 4 * N / (kper * 1e-3) / 1e9, 1),
+            "distributions_GB": round(19 * 4 * N / 1e9, 1), "mass_finite": bool(np.isfinite(s).all())}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -294,6 +330,9 @@ def main():
         print("[bench] FP16/BF16 storage runs", file=sys.stderr, flush=True)
         sw = storage_sweep(a.size, 40)
         out["reduced_precision"] = {"MLUPS": sw, "speedup_vs_f32": {k: round(v / mlups, 3) for k, v in sw.items()}}
+    if a.storage == "f32" and a.scheme == "swap2" and not a.no_large:
+        print("[bench] 1024^3 single-copy run", file=sys.stderr, flush=True)
+        out["large_1024"] = large_run(1024, 50)
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
         out["adjoint"] = {"workload": adjoint_ratio((128, 64, 64), 200, 20),

@@ -247,9 +247,57 @@ static hipError_t prepass_t(const Geom& g, const MarchPlan& p, const void* f, vo
     long long blocks = (total + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 16384) blocks = 16384;
+    const int nflags = p.nty * p.ntz * p.nseg + 1;  // every tile of every round, and the timeout word
     hipLaunchKernelGGL(k_prepass<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
-                       static_cast<T*>(side), flags, p.blocks + 1, p.flag_stride, p.M, p.seg_len, p.nseg);
+                       static_cast<T*>(side), flags, nflags, p.flag_stride, p.M, p.seg_len, p.nseg);
     return hipGetLastError();
+}
+
+// The M boundary rows of every band of tile rows, at time t, before a pass in
+// rounds: shell[((band * 2 + part) * nx + x) * Q + q][row][z], part 0 the
+// band's first M rows, part 1 its last M rows.
+template <class T>
+__global__ __launch_bounds__(256) void k_shells(Geom g, const T* __restrict__ f, T* __restrict__ shell, int M,
+                                                int band_rows, int nbands)
+{
+    const long long rowlen = (long long)M * g.nz;
+    const long long total = (long long)nbands * 2 * g.nx * Q * rowlen;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        long long r = t;
+        const int z = int(r % g.nz);
+        r /= g.nz;
+        const int row = int(r % M);
+        r /= M;
+        const int q = int(r % Q);
+        r /= Q;
+        const int x = int(r % g.nx);
+        r /= g.nx;
+        const int part = int(r % 2), band = int(r / 2);
+        const int y0 = band * band_rows, y1 = min(g.ny, y0 + band_rows);
+        const int y = part == 0 ? y0 + row : y1 - M + row;
+        shell[t] = f[q * g.N + ((long long)x * g.ny + y) * g.nz + z];
+    }
+}
+
+template <class T>
+static hipError_t shells_t(const Geom& g, const MarchPlan& p, int TY, const void* f, void* shell, hipStream_t s)
+{
+    const long long total = (long long)p.nbands * 2 * g.nx * Q * p.M * g.nz;
+    long long blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_shells<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
+                       static_cast<T*>(shell), p.M, p.nty_band * TY, p.nbands);
+    return hipGetLastError();
+}
+
+hipError_t launch_shells(int storage, const Geom& g, const MarchPlan& p, int TY, const void* f, void* shell,
+                         hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return shells_t<double>(g, p, TY, f, shell, s);
+    case ST_F32: return shells_t<float>(g, p, TY, f, shell, s);
+    default: return shells_t<uint16_t>(g, p, TY, f, shell, s);
+    }
 }
 
 hipError_t launch_prepass(int storage, const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags,

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,7 +25,10 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     MarchPlan plan[3];  // indexed by M
-    size_t off_partials = 0, off_sums = 0, off_second = 0, off_flags = 0, off_side = 0;
+    size_t off_partials = 0, off_sums = 0, off_second = 0, off_flags = 0, off_side = 0, off_shell = 0;
+    // the timeout word is meaningful once an in-place pass (whose prepass clears
+    // it) has run: the work buffer arrives uninitialised
+    bool guarded_pass = false;
     // measurement hook: event pairs around update-kernel launches
     bool timing = false;
     std::vector<hipEvent_t> ev;  // 2 per recorded launch, reused
@@ -92,16 +96,28 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     r.nty = (c.ny + r.TY - 1) / r.TY;
     r.ntz = (c.nz + r.TZ - 1) / r.TZ;
     const int tiles = r.nty * r.ntz;
-    if (tiles > cap)
-        return fail(why, LBM_EUNSUPPORTED,
-                    "the y-z plane needs more marching workgroups (" + std::to_string(tiles) +
-                        ") than can be co-resident (" + std::to_string(cap) + ")");
-    // a periodic axis whose last tile is thinner than M lets halos reach two tiles away
     const bool py = c.face[2] == LBM_PERIODIC, pz = c.face[4] == LBM_PERIODIC;
+    r.nbands = 1;
+    r.nty_band = r.nty;
+    if (tiles > cap) {
+        // rounds over bands of tile rows, each band's boundary rows saved first
+        const std::string need = "the y-z plane needs " + std::to_string(tiles) +
+                                 " marching workgroups, more than can be co-resident (" + std::to_string(cap) + ")";
+        if (!r.pr) return fail(why, LBM_EUNSUPPORTED, need + ", and this kernel layout has no rounds");
+        if (r.ntz > cap) return fail(why, LBM_EUNSUPPORTED, need + ", even for one row of tiles");
+        if (py && c.ny % r.TY != 0)
+            return fail(why, LBM_EUNSUPPORTED, need + "; rounds on a periodic y axis need whole tile rows");
+        r.nty_band = cap / r.ntz;
+        r.nbands = (r.nty + r.nty_band - 1) / r.nty_band;
+        if (c.ny - (r.nbands - 1) * r.nty_band * r.TY < M)
+            return fail(why, LBM_EUNSUPPORTED, need + "; the last band of rows is thinner than the halo");
+    }
+    const int tiles_run = r.nty_band * r.ntz;  // work items of one round, per segment
+    // a periodic axis whose last tile is thinner than M lets halos reach two tiles away
     r.ry = (py && r.nty > 1 && c.ny % r.TY != 0 && c.ny % r.TY < M) ? 2 : 1;
     r.rz = (pz && r.ntz > 1 && c.nz % r.TZ != 0 && c.nz % r.TZ < M) ? 2 : 1;
     // x segments: as many as fit, each at least 4M planes long
-    int nseg = cap / tiles;
+    int nseg = cap / tiles_run;
     const int by_len = c.nx / (4 * M);
     if (nseg > by_len) nseg = by_len;
     if (nseg < 1) nseg = 1;
@@ -114,11 +130,14 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     }
     r.nseg = nseg;
     r.seg_len = seg_len;
-    r.blocks = tiles * nseg;
+    r.blocks = tiles_run * nseg;
     r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
     r.side_bytes = size_t(nseg) * size_t(M) * 19u * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
+    r.shell_bytes = r.nbands > 1 ? size_t(r.nbands) * 2u * size_t(M) * size_t(c.nz) * size_t(c.nx) * 19u *
+                                       elem_size(c.storage)
+                                 : 0;
     r.flag_stride = kFlagStride;
-    r.flag_bytes = size_t(r.blocks + 1) * size_t(kFlagStride) * sizeof(int);
+    r.flag_bytes = size_t(tiles * nseg + 1) * size_t(kFlagStride) * sizeof(int);
     *p = r;
     return LBM_OK;
 }
@@ -152,7 +171,7 @@ lbm_status validate(const lbm_config* c, std::string* why)
 }
 
 // work buffer layout; plans use the device's co-residency cap
-lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[3], size_t off[5], size_t* total, std::string* why)
+lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[3], size_t off[6], size_t* total, std::string* why)
 {
     const long long N = (long long)c.nx * c.ny * c.nz;
     size_t o = 0;
@@ -160,23 +179,26 @@ lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[3], size_t off[5
     o = align_up(o + size_t(SUM_BLOCKS) * 4 * sizeof(double));
     off[1] = o;  // final sums
     o = align_up(o + 4 * sizeof(double));
-    off[2] = off[3] = off[4] = 0;
+    off[2] = off[3] = off[4] = off[5] = 0;
     if (c.scheme == LBM_TWO_ARRAY) {
         off[2] = o;  // the second lattice of the plain scheme
         o = align_up(o + size_t(19) * size_t(N) * elem_size(c.storage));
     } else {
-        size_t flags = 0, side = 0;
+        size_t flags = 0, side = 0, shell = 0;
         for (int M = 1; M <= 2; ++M) {
             if (M == 2 && c.scheme != LBM_SWAP2) continue;
             lbm_status st = make_plan(c, M, cap, &plans[M], why);
             if (st != LBM_OK) return st;
             if (plans[M].flag_bytes > flags) flags = plans[M].flag_bytes;
             if (plans[M].side_bytes > side) side = plans[M].side_bytes;
+            if (plans[M].shell_bytes > shell) shell = plans[M].shell_bytes;
         }
         off[3] = o;
         o = align_up(o + flags);
         off[4] = o;
         o = align_up(o + side);
+        off[5] = o;
+        o = align_up(o + shell);
     }
     *total = o;
     return LBM_OK;
@@ -239,8 +261,16 @@ lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void
         if (cfg->face[fc] == LBM_MOVING_WALL) g.moving_face = fc;
     g.omega = 1.0 / cfg->tau;
 
-    size_t off[5], total = 0;
+    size_t off[6], total = 0, sized = 0;
     int cap = kMaxResident;
+    {
+        MarchPlan probe[3];
+        st = layout(*cfg, cap, probe, off, &sized, &g_create_err);  // what lbm_buffer_sizes reported
+        if (st != LBM_OK) {
+            delete ctx;
+            return st;
+        }
+    }
     if (cfg->scheme != LBM_TWO_ARRAY) {
         // the device may hold fewer marching workgroups than the sizing bound
         MarchPlan probe[3];
@@ -264,11 +294,17 @@ lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void
         delete ctx;
         return st;
     }
+    if (total > sized) {
+        delete ctx;
+        return fail(&g_create_err, LBM_EUNSUPPORTED,
+                    "this device holds fewer co-resident marching workgroups than the work-buffer size assumed");
+    }
     ctx->off_partials = off[0];
     ctx->off_sums = off[1];
     ctx->off_second = off[2];
     ctx->off_flags = off[3];
     ctx->off_side = off[4];
+    ctx->off_shell = off[5];
     *out = ctx;
     return LBM_OK;
 }
@@ -309,10 +345,17 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
     int* flags = reinterpret_cast<int*>(ctx->work + ctx->off_flags);
     void* side = ctx->work + ctx->off_side;
     const bool inplace = src == dst;
+    unsigned char* shell = ctx->work + ctx->off_shell;
     if (inplace) {
         lbm_status st = device_err(ctx, launch_prepass(ctx->cfg.storage, ctx->g, p, src, side, flags, ctx->stream),
                                    "prepass launch");
         if (st != LBM_OK) return st;
+        ctx->guarded_pass = true;
+        if (p.nbands > 1) {
+            st = device_err(ctx, launch_shells(ctx->cfg.storage, ctx->g, p, p.TY, src, shell, ctx->stream),
+                            "band boundary copy launch");
+            if (st != LBM_OK) return st;
+        }
     }
     MarchArgs a;
     a.g = ctx->g;
@@ -332,13 +375,26 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
     a.fstride = p.flag_stride;
     const bool walls = ctx->g.wall[0] || ctx->g.wall[1] || ctx->g.wall[2];
     const bool force = ctx->force != nullptr;
-    hipError_t e;
+    const size_t part = size_t(ctx->g.nx) * 19u * size_t(M) * size_t(ctx->g.nz) * elem_size(ctx->cfg.storage);
+    const bool py = ctx->cfg.face[2] == LBM_PERIODIC;
+    hipError_t e = hipSuccess;
     const long tix = timing_begin(ctx, M);
-    switch (ctx->cfg.storage) {
-    case LBM_F64: e = launch_march_f64(walls, force, p, a, ctx->stream); break;
-    case LBM_F32: e = launch_march_f32(walls, force, p, a, ctx->stream); break;
-    case LBM_F16_OFS: e = launch_march_f16(walls, force, p, a, ctx->stream); break;
-    default: e = launch_march_bf16(walls, force, p, a, ctx->stream); break;
+    for (int b = 0; b < p.nbands && e == hipSuccess; ++b) {
+        // one round: a band of tile rows; with one band, the whole plane
+        MarchPlan pb = p;
+        a.band_ty0 = b * p.nty_band;
+        a.nty_band = std::min(p.nty_band, p.nty - a.band_ty0);
+        a.shell_lo = (inplace && b > 0) ? shell + (size_t(2 * (b - 1) + 1)) * part : nullptr;
+        a.shell_hi = (inplace && p.nbands > 1 && b == p.nbands - 1 && py) ? shell : nullptr;
+        pb.blocks = a.nty_band * p.ntz * p.nseg;
+        pb.xcd_remap = (pb.blocks % 8 == 0) ? 1 : 0;
+        a.xcd_remap = pb.xcd_remap;
+        switch (ctx->cfg.storage) {
+        case LBM_F64: e = launch_march_f64(walls, force, pb, a, ctx->stream); break;
+        case LBM_F32: e = launch_march_f32(walls, force, pb, a, ctx->stream); break;
+        case LBM_F16_OFS: e = launch_march_f16(walls, force, pb, a, ctx->stream); break;
+        default: e = launch_march_bf16(walls, force, pb, a, ctx->stream); break;
+        }
     }
     timing_end(ctx, tix);
     return device_err(ctx, e, "marching kernel launch");
@@ -354,7 +410,7 @@ lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work
     lbm_status st = validate(cfg, &why);
     if (st != LBM_OK) return st;
     MarchPlan plans[3];
-    size_t off[5], total = 0;
+    size_t off[6], total = 0;
     st = layout(*cfg, kMaxResident, plans, off, &total, &why);
     if (st != LBM_OK) return st;
     if (f_bytes) *f_bytes = size_t(19) * size_t(cfg->nx) * size_t(cfg->ny) * size_t(cfg->nz) * elem_size(cfg->storage);
@@ -476,7 +532,7 @@ lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double*
     st = device_err(ctx, hipMemcpyAsync(sums_host, sums, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
                     "sums copy");
     int timeout = 0;
-    if (st == LBM_OK && ctx->cfg.scheme != LBM_TWO_ARRAY)
+    if (st == LBM_OK && ctx->cfg.scheme != LBM_TWO_ARRAY && ctx->guarded_pass)
         st = device_err(ctx,
                         hipMemcpyAsync(&timeout, ctx->work + ctx->off_flags, sizeof(int), hipMemcpyDeviceToHost,
                                        ctx->stream),

@@ -33,6 +33,10 @@ struct MarchPlan {
     size_t side_bytes = 0;       // side planes: nseg * M planes * 19 values
     int flag_stride = 1;         // ints between two progress counters
     size_t flag_bytes = 0;       // timeout word + one counter per work item
+    // y-z planes with more tiles than can be co-resident run as rounds over
+    // bands of nty_band tile rows (pair-and-ring kernel only)
+    int nbands = 1, nty_band = 0;
+    size_t shell_bytes = 0;      // the M boundary rows of every band, all x: nbands * 2 * M rows
 };
 
 struct MarchArgs {
@@ -44,7 +48,13 @@ struct MarchArgs {
     const void* force;  // 3N or null
     int* flags;         // progress (planes loaded) of every work item
     int nty, ntz, nseg, seg_len, ry, rz, xcd_remap;
-    int fstride;  // ints between two progress counters (counter of work item w at flags[(1 + w) * fstride])
+    int fstride;  // ints between two progress counters (counter of tile (seg, ty, tz) at
+                  // flags[(1 + (seg * nty + ty) * ntz + tz) * fstride])
+    // round over a band of tile rows [band_ty0, band_ty0 + nty_band); halo rows
+    // of bands already updated come from their saved boundary rows
+    int band_ty0, nty_band;
+    const void* shell_lo;  // rows below the band: [x][q][M][nz] copy, or null (read f)
+    const void* shell_hi;  // rows above the band, likewise
 };
 
 // One merged two-step adjoint pass (out of place).
@@ -65,6 +75,8 @@ hipError_t launch_two_array(int storage, bool force, const Geom& g, const void* 
 hipError_t launch_copy(int storage, const Geom& g, const void* src, void* dst, hipStream_t s);
 hipError_t launch_prepass(int storage, const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags,
                           hipStream_t s);
+hipError_t launch_shells(int storage, const Geom& g, const MarchPlan& p, int TY, const void* f, void* shell,
+                         hipStream_t s);
 
 constexpr int SUM_BLOCKS = 1024;  // fixed grid of the reduction: deterministic order
 hipError_t launch_macro(int storage, bool force, const Geom& g, const void* f, const void* F, double* rho, double* u,

@@ -231,28 +231,45 @@ struct PairRingShape {
     static constexpr int NT = TY * TZ / 2;  // one interior pair per thread
     static constexpr int RING = NC - TY * TZ;
     static constexpr int WZ2 = TZ + 2, NC2 = (TY + 2) * WZ2;
+    // The ring in rounds (bands of tile rows): rows below the tile, the side
+    // columns and rows above each fill whole waves, so that the source of a
+    // wave's ring loads (the lattice or a saved band boundary) is uniform.
+    static constexpr int B1 = (M * WZ + 63) / 64 * 64;               // side columns start
+    static constexpr int B2 = (B1 + TY * 2 * M + 63) / 64 * 64;      // rows above start
+    static constexpr int RINGB = B2 + M * WZ;
     static_assert(TZ % 2 == 0, "pairs need an even tile width");
     static_assert(RING <= NT, "at most one ring column per thread");
+    static_assert(RINGB <= NT, "the banded ring layout fits the workgroup");
 };
 
-// local (ly, lz) of ring cell r, row-major over the frame of the full tile
+// local (ly, lz) of ring slot r: rows below the tile, side columns, rows
+// above, row-major; in rounds each part starts on a wave boundary (slots in
+// between are empty: returns false)
 template <int M, int TY, int TZ>
-__device__ __forceinline__ void ring_cell(int r, int& ly, int& lz)
+__device__ __forceinline__ bool ring_cell(int r, bool banded, int& ly, int& lz)
 {
+    using Sh = PairRingShape<M, TY, TZ>;
     constexpr int WZ = TZ + 2 * M;
+    const int b1 = banded ? Sh::B1 : M * WZ, b2 = banded ? Sh::B2 : M * WZ + TY * 2 * M;
     if (r < M * WZ) {
         ly = r / WZ;
         lz = r - ly * WZ;
-    } else if (r < M * WZ + TY * 2 * M) {
-        const int rr = r - M * WZ;
+        return true;
+    }
+    if (r >= b1 && r < b1 + TY * 2 * M) {
+        const int rr = r - b1;
         ly = M + rr / (2 * M);
         const int k = rr - (rr / (2 * M)) * (2 * M);
         lz = k < M ? k : TZ + k;
-    } else {
-        const int rr = r - M * WZ - TY * 2 * M;
+        return true;
+    }
+    if (r >= b2 && r < b2 + M * WZ) {
+        const int rr = r - b2;
         ly = M + TY + rr / WZ;
         lz = rr - (rr / WZ) * WZ;
+        return true;
     }
+    return false;
 }
 
 template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
@@ -262,7 +279,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     using T = typename Cd::T;
     using R = typename Cd::R;
     using Sh = PairRingShape<M, TY, TZ>;
-    constexpr int WZ = Sh::WZ, NC = Sh::NC, NT = Sh::NT, RING = Sh::RING, WZ2 = Sh::WZ2, NC2 = Sh::NC2;
+    constexpr int WZ = Sh::WZ, NC = Sh::NC, WZ2 = Sh::WZ2, NC2 = Sh::NC2;
     constexpr int NB1 = (M == 1) ? 2 : 1;
     constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
     static_assert(M == 1 || M == 2, "one or two merged steps");
@@ -281,7 +298,9 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         const int per = gridDim.x >> 3;
         wid = (wid & 7) * per + (wid >> 3);
     }
-    const int tz = wid % a.ntz, ty = (wid / a.ntz) % a.nty, seg = wid / (a.ntz * a.nty);
+    const bool banded = a.nty_band < a.nty;
+    const int tz = wid % a.ntz, ty = a.band_ty0 + (wid / a.ntz) % a.nty_band, seg = wid / (a.ntz * a.nty_band);
+    const long long gtile = ((long long)seg * a.nty + ty) * a.ntz + tz;  // progress counter index
     const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
     const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);
     const bool wallx = g.wall[0] != 0;
@@ -310,6 +329,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     constexpr int K = 3;
     int gofs[K], rad[K], ci[K], ci2[K];
     uint32_t voff[K], byz[K];
+    uint32_t shoff = kOffNone;  // ring column in a band boundary copy: (row * nz + z) * sizeof(T)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         gofs[k] = -1;
@@ -323,10 +343,8 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         if (k < 2) {
             ly = M + tid / (TZ / 2);
             lz = M + 2 * (tid - (tid / (TZ / 2)) * (TZ / 2)) + k;
-        } else if (tid < RING) {
-            ring_cell<M, TY, TZ>(tid, ly, lz);
         } else {
-            have = false;
+            have = ring_cell<M, TY, TZ>(tid, banded, ly, lz);
         }
         if (!have) continue;
         ci[k] = ly * WZ + lz;
@@ -344,6 +362,10 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         voff[k] = uint32_t(gofs[k]) * uint32_t(sizeof(T));
         rad[k] = dy > dz ? dy : dz;
         ci2[k] = (ly - 1) * WZ2 + (lz - 1);
+        if (k == 2 && (ly < M || ly >= M + TYe)) {
+            const int row = ly < M ? ly : ly - (M + TYe);
+            shoff = uint32_t(row * g.nz + z) * uint32_t(sizeof(T));
+        }
         if constexpr (WALLS) {
             uint32_t b = 0, mv = 0;
             sfor<1, Q>([&](auto qc) {
@@ -369,7 +391,17 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     const bool pair_loads = rad[0] <= M && gofs[0] >= 0;
     const uint32_t loffP = pair_loads ? voff[0] : kOffNone;
     const uint32_t soffP = (rad[0] == 0 && gofs[0] >= 0) ? voff[0] : kOffNone;
-    const uint32_t loffG = (rad[2] <= M && gofs[2] >= 0) ? voff[2] : kOffNone;
+    // in a round, a wave of ring rows below (above) the band reads the saved
+    // boundary rows of the band there when that band was already updated
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const T* shell_w = nullptr;
+    if (banded) {  // only the band's first (last) row of tiles borders the band below (above)
+        if (wave < Sh::B1 / 64 && ty == a.band_ty0) shell_w = static_cast<const T*>(a.shell_lo);
+        else if (wave >= Sh::B2 / 64 && ty == a.band_ty0 + a.nty_band - 1) shell_w = static_cast<const T*>(a.shell_hi);
+    }
+    const bool ring_loads = rad[2] <= M && gofs[2] >= 0;
+    const uint32_t loffG = ring_loads ? voff[2] : kOffNone;              // in the lattice or the side planes
+    const uint32_t loffS = (ring_loads && shell_w) ? shoff : kOffNone;  // in a saved band boundary
     const uint32_t loffPR = pair_loads ? uint32_t(gofs[0]) * uint32_t(sizeof(R)) : kOffNone;
     const uint32_t loffGR = (rad[2] <= M && gofs[2] >= 0) ? uint32_t(gofs[2]) * uint32_t(sizeof(R)) : kOffNone;
 
@@ -467,10 +499,16 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         const bool live = wanted && present(xp);
         long long qs;
         const T* bq = plane_base(xp, qs);
-        const uint32_t range = live ? plane_bytes : 0u;
+        uint32_t range = live ? plane_bytes : 0u, off = loffG;
+        if (shell_w && !(a.inplace && xp >= e && has_next)) {  // (the side planes hold every row at time t)
+            qs = (long long)M * g.nz;
+            bq = shell_w + (long long)wrapi(xp, g.nx) * Q * qs;
+            range = live ? uint32_t(qs) * uint32_t(sizeof(T)) : 0u;
+            off = loffS;
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            L[q] = Buf<T>::ld(make_rsrc(bq, range), loffG);
+            L[q] = Buf<T>::ld(make_rsrc(bq, range), off);
             bq += qs;
         }
         load_force(xp, live, Fb[2], loffGR);
@@ -497,6 +535,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         } else {
             yy = wrapi(yy, a.nty);
         }
+        if (yy < a.band_ty0 || yy >= a.band_ty0 + a.nty_band) fkind = 0;  // not in this round
         if (g.wall[2]) {
             if (zz < 0 || zz >= a.ntz) fkind = 0;
         } else {
@@ -604,7 +643,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             collide1(std::integral_constant<int, 2>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
         load_ring(xl + PF, next_wanted, Lg[pb], Fl1[pb]);
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.flags + (1 + (long long)wid) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.flags + (1 + gtile) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----

@@ -93,6 +93,33 @@ def random_phases(seed):
     return tuple(float(p) for p in rng.uniform(0.0, 2 * math.pi, size=3))
 
 
+def taylor_green_3d_at(shape, u0, phase, ix, iy, iz):
+    """The Taylor-Green field of taylor_green_3d on the index grid ix x iy x iz
+    (1-D integer arrays): u of shape (3, len(ix), len(iy), len(iz))."""
+    X = (2 * math.pi * np.asarray(ix, np.float64) / shape[0] + phase[0])[:, None, None]
+    Y = (2 * math.pi * np.asarray(iy, np.float64) / shape[1] + phase[1])[None, :, None]
+    Z = (2 * math.pi * np.asarray(iz, np.float64) / shape[2] + phase[2])[None, None, :]
+    u = np.zeros((3, len(ix), len(iy), len(iz)))
+    u[0] = u0 * np.sin(X) * np.cos(Y) * np.cos(Z)
+    u[1] = -u0 * np.cos(X) * np.sin(Y) * np.cos(Z)
+    return u
+
+
+def taylor_green_3d_device(shape, u0, phase, device):
+    """The same field built directly in device memory (float64 torch tensor of
+    shape (3, nx, ny, nz)), for lattices whose fields are too large for the
+    host.  Same formula as taylor_green_3d_at, evaluated by torch."""
+    import torch
+    ax = [(2 * math.pi * torch.arange(n, dtype=torch.float64, device=device)) / n + p for n, p in zip(shape, phase)]
+    sx, cx = torch.sin(ax[0])[:, None, None], torch.cos(ax[0])[:, None, None]
+    sy, cy = torch.sin(ax[1])[None, :, None], torch.cos(ax[1])[None, :, None]
+    cz = torch.cos(ax[2])[None, None, :]
+    u = torch.zeros((3,) + tuple(shape), dtype=torch.float64, device=device)
+    u[0] = ((u0 * sx) * cy) * cz
+    u[1] = ((-u0 * cx) * sy) * cz
+    return u
+
+
 def sample_cells(shape, count, seed):
     """``count`` distinct cell indices (x, y, z) drawn with default_rng(seed)."""
     rng = np.random.default_rng(seed)

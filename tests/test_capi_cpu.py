@@ -40,7 +40,10 @@ def _status(cfg):
     (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(storage=capi.LBM_F16_OFS, use_force=True), capi.LBM_EUNSUPPORTED),
     (dict(variant=99), capi.LBM_EUNSUPPORTED),
-    (dict(shape=(64, 1024, 1024)), capi.LBM_EUNSUPPORTED),
+    # more tiles than co-resident workgroups: FP64's plain layout has no rounds
+    (dict(shape=(64, 1024, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
+    # rounds on a periodic y axis need whole tile rows (16 rows per tile)
+    (dict(shape=(64, 1000, 1024)), capi.LBM_EUNSUPPORTED),
 ])
 def test_invalid_configs_are_rejected(kw, code):
     assert _status(_cfg(**kw))[0] == code
@@ -55,6 +58,19 @@ def test_buffer_sizes():
     st, fb, wb2 = _status(_cfg(scheme=capi.LBM_SWAP2))
     assert wb2 < fb  # single copy: the work buffer is a small fraction of the lattice
     assert _status(_cfg(shape=(512, 512, 512)))[0] == capi.LBM_OK
+
+
+def test_rounds_plan_for_large_planes():
+    # 1024^2 planes need 1024 tiles of 16x64: four rounds of 256 tile rows' bands;
+    # the work buffer holds 2 M boundary rows of every band for all x
+    nx = 64
+    st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024)))
+    assert st == capi.LBM_OK
+    shells = 4 * 2 * 2 * 1024 * nx * 19 * 4
+    assert shells <= wb < shells + 19 * 4 * 1024 * 1024 * 4 + (1 << 24)
+    # with walls in y any row count works (the last band may end in a partial tile)
+    walls = (0, 0, capi.LBM_WALL, capi.LBM_WALL, 0, 0)
+    assert _status(_cfg(shape=(nx, 1000, 1024), faces=walls))[0] == capi.LBM_OK
 
 
 def test_null_and_state_errors():

@@ -39,10 +39,15 @@ def cone_box(shape, faces, center, n):
 
 
 def oracle_center(rho0, u0, shape, faces, wall_u, tau, center, n):
+    """u0: the full initial velocity array, or a function of the box's index
+    arrays (ix, iy, iz) returning it on that box."""
     idx, bfaces, pos = cone_box(shape, faces, center, n)
     ix = np.ix_(*idx)
     r = None if rho0 is None else np.ascontiguousarray(rho0[ix])
-    u = None if u0 is None else np.ascontiguousarray(np.stack([u0[c][ix] for c in range(3)]))
+    if callable(u0):
+        u = np.ascontiguousarray(u0(*idx))
+    else:
+        u = None if u0 is None else np.ascontiguousarray(np.stack([u0[c][ix] for c in range(3)]))
     bshape = tuple(len(i) for i in idx)
     o = Oracle(bshape, tau, faces=bfaces, wall_u=wall_u)
     f = o.run(o.init(r, u), n)
@@ -100,3 +105,92 @@ def test_cavity256_fp32_sampled_cells(scheme):
         ref = oracle_center(None, None, shape, faces, wall_u, tau, c, n)
         assert np.abs(g - ref).max() <= 2e-7, c
     lat.close()
+
+
+# y-z planes with more 16x64 tiles than co-resident workgroups run as rounds
+# over bands of tile rows (their boundary rows saved before the pass)
+BANDED_CASES = [
+    ((12, 272, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),                          # 17 x 16 tiles, 2 rounds
+    ((10, 280, 1030), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),  # ragged, lid on +y
+    ((9, 288, 1040), (WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.0, 0.0)),  # periodic y across rounds
+]
+_NAMES = {PERIODIC: "periodic", WALL: "wall", MOVING_WALL: "moving"}
+
+
+@pytest.mark.parametrize("case", range(len(BANDED_CASES)))
+def test_rounds_match_two_array_bitwise(case):
+    shape, faces, wall_u = BANDED_CASES[case]
+    names = [_NAMES[f] for f in faces]
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, 400 + case)
+    r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 401 + case)), torch.as_tensor(u0)
+    print(f"[gpu] rounds {shape} {names}", flush=True)
+    ref = Lattice(shape, 0.6, "f32", "two_array", names, wall_u, rho0=r0, u0=v0)
+    for scheme in ("swap2", "swap1"):
+        lat = Lattice(shape, 0.6, "f32", scheme, names, wall_u, rho0=r0, u0=v0)
+        for n in (3, 2):  # odd counts end with a single-step round
+            ref_f0 = ref.f.clone()
+            lat.f.copy_(ref_f0)
+            ref.step(n)
+            lat.step(n)
+            torch.cuda.synchronize()
+            assert torch.equal(lat.f.view(torch.int32), ref.f.view(torch.int32)), (scheme, n)
+            # out of place, from the same start
+            dst = torch.empty_like(lat.f)
+            lat.step_into(ref_f0, dst, 2)
+            ref2 = Lattice(shape, 0.6, "f32", "two_array", names, wall_u, f=ref_f0.clone())
+            ref2.step(2)
+            torch.cuda.synchronize()
+            assert torch.equal(dst.view(torch.int32), ref2.f.view(torch.int32)), (scheme, "into")
+            ref2.close()
+        lat.close()
+    ref.close()
+
+
+def test_rounds_sampled_cells_vs_oracle():
+    shape, faces, wall_u = BANDED_CASES[2]
+    names = [_NAMES[f] for f in faces]
+    n = 4
+    _, u0 = wl.taylor_green_3d(shape, 0.03)
+    lat = Lattice(shape, 0.6, "f32", "swap2", names, wall_u, u0=torch.as_tensor(u0))
+    lat.step(n)
+    torch.cuda.synchronize()
+    # cells on band and tile boundaries (band rows 0-255 | 256-287), the periodic y seam and the x walls
+    cells = [(0, 255, 0), (4, 256, 63), (8, 254, 64), (3, 257, 1039), (5, 0, 500), (6, 287, 511), (0, 286, 2),
+             (8, 1, 1038)] + wl.sample_cells(shape, 6, 9)
+    got = gpu_cells(lat, cells)
+    for c, gv in zip(cells, got):
+        ref = oracle_center(None, u0, shape, faces, wall_u, 0.6, c, n)
+        assert np.abs(gv - ref).max() <= 2e-7, c
+    lat.close()
+
+
+def test_tgv1024_fp32_merged_rounds_sampled_cells():
+    # the large single-copy run: 1024^3 FP32 (81.6 GB of distributions), four
+    # rounds of 256 tiles per merged pass, random-phase Taylor-Green field
+    cfg = wl.TGV_1024
+    shape, tau, n = cfg["shape"], cfg["tau"], 4
+    ph = wl.random_phases(cfg["phase_seed"])
+    print(f"[gpu] 1024^3 f32 swap2 rounds, {n} steps", flush=True)
+    u0 = wl.taylor_green_3d_device(shape, cfg["u0"], ph, "cuda")
+    lat = Lattice(shape, tau, "f32", "swap2", u0=u0)
+    del u0
+    torch.cuda.empty_cache()
+    s0 = lat.sums()
+    lat.step(n)
+    torch.cuda.synchronize()
+    s1 = lat.sums()
+    # band seams (rows 255/256, 511/512, 767/768, 1023/0), tile seams and the x wrap
+    cells = [(0, 255, 0), (1, 256, 63), (1023, 511, 64), (512, 512, 1023), (7, 767, 500), (100, 768, 511),
+             (1023, 1023, 1), (0, 0, 1022)] + wl.sample_cells(shape, 8, 11)
+    got = gpu_cells(lat, cells)
+    ufn = lambda ix, iy, iz: wl.taylor_green_3d_at(shape, cfg["u0"], ph, ix, iy, iz)  # noqa: E731
+    faces = (PERIODIC,) * 6
+    for c, g in zip(cells, got):
+        ref = oracle_center(None, ufn, shape, faces, (0, 0, 0), tau, c, n)
+        assert np.abs(g - ref).max() <= 2e-7, c
+    assert abs(s1[0] - s0[0]) <= 1e-9 * s0[0]
+    assert np.abs(s1[1:] - s0[1:]).max() <= 1e-9 * s0[0]
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()

@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--scheme", default="swap2", choices=["swap2", "swap1", "two_array"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
     ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "cavity", "large"],
+                    help="tgv: the periodic Taylor-Green + noise workload (tau 0.6); cavity: lid-driven cavity "
+                         "(tau 0.52, five walls, +y lid at 0.05 along x, rest state); large: periodic random-phase "
+                         "Taylor-Green (tau 0.55, seed 4) built on the device, for 1024^3")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
@@ -241,13 +245,30 @@ def main():
 
     shape = (a.size,) * 3
     N = int(np.prod(shape))
-    tau = wl.TGV_512["tau"]
-    print(f"[bench] building {shape} {a.storage} {a.scheme} fields", file=sys.stderr, flush=True)
-    _, u0 = wl.tgv_512_fields(shape)
-    u0_dev = torch.from_numpy(u0).to("cuda")
-    del u0
-    lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
-    del u0_dev
+    print(f"[bench] building {shape} {a.storage} {a.scheme} {a.workload}", file=sys.stderr, flush=True)
+    if a.workload == "cavity":
+        tau = wl.CAVITY_256["tau"]
+        lat = Lattice(shape, tau, a.storage, a.scheme, ("wall", "wall", "wall", "moving", "wall", "wall"),
+                      (wl.CAVITY_256["lid_u"], 0.0, 0.0), variant=a.variant)
+        wdesc = (f"{a.size}^3 lid-driven cavity D3Q19 BGK tau={tau}, halfway bounce-back on 5 walls, +y lid "
+                 f"u=({wl.CAVITY_256['lid_u']},0,0), rest state, {a.storage} storage")
+    elif a.workload == "large":
+        cfg = wl.TGV_1024
+        tau = cfg["tau"]
+        u0_dev = wl.taylor_green_3d_device(shape, cfg["u0"], wl.random_phases(cfg["phase_seed"]), "cuda")
+        lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
+        del u0_dev
+        wdesc = (f"{a.size}^3 periodic D3Q19 BGK tau={tau}, random-phase Taylor-Green u0={cfg['u0']} (seed "
+                 f"{cfg['phase_seed']}), {a.storage} storage")
+    else:
+        tau = wl.TGV_512["tau"]
+        _, u0 = wl.tgv_512_fields(shape)
+        u0_dev = torch.from_numpy(u0).to("cuda")
+        del u0
+        lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
+        del u0_dev
+        wdesc = (f"{a.size}^3 periodic D3Q19 BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
+                 f"(seed 20805429), {a.storage} storage")
     torch.cuda.empty_cache()
     print(f"[bench] warmup {a.warmup} steps", file=sys.stderr, flush=True)
     lat.step(a.warmup)
@@ -277,7 +298,9 @@ def main():
     s = BYTES[a.storage]
     alg_bytes = 2 * 19 * s * N  # one read and one write of the single copy per launch
     achieved = alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
-    kernel_key = f"march_M{M}_{a.storage}_{a.size}" if a.scheme != "two_array" else f"two_array_{a.storage}_{a.size}"
+    kernel_key = (f"march_M{M}_{a.storage}_{a.size}" if a.scheme != "two_array" else f"two_array_{a.storage}_{a.size}")
+    if a.workload != "tgv":
+        kernel_key += "_" + a.workload
     traffic = traffic_entry(kernel_key)
     out = {
         "metric": METRIC,
@@ -292,8 +315,7 @@ def main():
         "vs_baseline": None,
         "dtype": a.storage,
         "data": "synthetic",
-        "config": {"workload": f"{a.size}^3 periodic D3Q19 BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
-                               f"(seed 20805429), {a.storage} storage",
+        "config": {"workload": wdesc,
                    "scheme": a.scheme, "steps_per_launch": M, "variant": a.variant,
                    "bytes_per_lattice_update": 2 * 19 * s / M},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -326,11 +348,12 @@ def main():
         out["copy_probe"] = {"bytes": a.copy_probe, "ms": round(best, 4)}
         del src, dst
         torch.cuda.empty_cache()
-    if a.storage == "f32" and a.scheme == "swap2" and not a.no_storage_sweep:
+    headline = a.storage == "f32" and a.scheme == "swap2" and a.workload == "tgv"
+    if headline and not a.no_storage_sweep:
         print("[bench] FP16/BF16 storage runs", file=sys.stderr, flush=True)
         sw = storage_sweep(a.size, 40)
         out["reduced_precision"] = {"MLUPS": sw, "speedup_vs_f32": {k: round(v / mlups, 3) for k, v in sw.items()}}
-    if a.storage == "f32" and a.scheme == "swap2" and not a.no_large:
+    if headline and not a.no_large:
         print("[bench] 1024^3 single-copy run", file=sys.stderr, flush=True)
         out["large_1024"] = large_run(1024, 50)
     if not a.no_adjoint:

@@ -228,3 +228,30 @@ def test_step_into_matches_in_place(storage, case):
             assert torch.equal(lat.f.view(torch.int8), dst.view(torch.int8)), (scheme, k)
             lat.f.copy_(ref)
         assert torch.equal(src.view(torch.int8), lat.f.view(torch.int8))
+
+
+# degenerate lattices: single cells, axes of length 1 and 2 (periodic axes
+# shorter than the halo wrap onto the tile itself), odd z (plain layout)
+DEGENERATE = [
+    ((1, 1, 1), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((2, 2, 2), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((1, 5, 6), (PERIODIC, PERIODIC, WALL, WALL, WALL, MOVING_WALL), (0.02, 0.01, 0.0)),
+    ((3, 1, 4), (WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.0, 0.0)),
+    ((5, 3, 1), (WALL, MOVING_WALL, WALL, WALL, PERIODIC, PERIODIC), (0.0, 0.03, 0.0)),
+    ((4, 2, 7), (WALL,) * 6, (0.0, 0.0, 0.0)),
+    ((9, 1, 2), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DEGENERATE)))
+def test_degenerate_lattices_match_oracle(case):
+    shape, faces, wall_u = DEGENERATE[case]
+    rho0, u0 = _noisy_init(shape, 500 + case)
+    o = Oracle(shape, 0.7, faces=faces, wall_u=wall_u)
+    for steps in (0, 1, 2, 5):
+        ref = o.run(o.init(rho0, u0), steps)
+        for scheme in SCHEMES:
+            lat, _, _, _ = gpu_run(shape, 0.7, "f64", scheme, faces, wall_u, rho0, u0, steps=steps)
+            assert rel(lat.distributions(), ref) <= 1e-12, (scheme, steps)
+            lat32, _, _, _ = gpu_run(shape, 0.7, "f32", scheme, faces, wall_u, rho0, u0, steps=steps)
+            assert rel(lat32.distributions(), ref) <= 2e-6, (scheme, steps)

@@ -118,13 +118,14 @@ def test_force_gradient_matches_central_differences_fp64():
 
 
 # Two merged reverse steps (one pass, f_{t+1} recomputed on chip) against two
-# single reverse steps of the oracle.  Shapes span several 16x16 (FP32) or 8x8
+# single reverse steps of the oracle.  Shapes span several 12x28 (FP32) or 8x8
 # (FP64) tiles with ragged last tiles and several x segments.
 MERGED_CASES = [
     ((40, 21, 19), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
     ((24, 18, 37), (PERIODIC,) * 6, (0.0, 0.0, 0.0), True),
     ((17, 20, 22), (WALL, WALL, WALL, 2, WALL, WALL), (0.04, 0.0, -0.01), True),
     ((19, 13, 26), (2, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.03, 0.02), False),
+    ((18, 30, 61), (WALL, WALL, PERIODIC, PERIODIC, WALL, 2), (0.02, 0.03, 0.0), True),
 ]
 
 

@@ -135,24 +135,34 @@ struct Codec<ST_F32> {
     static __device__ __forceinline__ R dec(T v) { return v; }
     static __device__ __forceinline__ T enc(R v) { return v; }
 };
+// The 16-bit codecs also encode two values into one 32-bit word (low half
+// first), the form a pair store writes.  Both round to nearest even; gfx950
+// converts a pair of floats in one instruction for either format.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <>
 struct Codec<ST_F16> {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     using T = uint16_t;
     using R = float;
     static __device__ __forceinline__ R dec(T v) { return __half2float(__ushort_as_half(v)); }
     static __device__ __forceinline__ T enc(R v) { return __half_as_ushort(__float2half_rn(v)); }
+    static __device__ __forceinline__ uint32_t enc2(R a, R b)
+    {
+        const f32x2 v = {a, b};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2));
+    }
 };
 template <>
 struct Codec<ST_BF16> {
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
     using T = uint16_t;
     using R = float;
     static __device__ __forceinline__ R dec(T v) { return __uint_as_float(uint32_t(v) << 16); }
-    static __device__ __forceinline__ T enc(R v)
+    static __device__ __forceinline__ T enc(R v) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
+    static __device__ __forceinline__ uint32_t enc2(R a, R b)
     {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return T((u >> 16) | 0x40u);  // quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);                                    // round to nearest even
-        return T(u >> 16);
+        const f32x2 v = {a, b};
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf2));
     }
 };
 

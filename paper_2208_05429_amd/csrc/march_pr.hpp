@@ -72,9 +72,10 @@ struct Buf2<uint16_t> {
     {
         return K == 0 ? uint16_t(p & 0xffffu) : uint16_t(p >> 16);
     }
-    static __device__ __forceinline__ void st(uint16_t a, uint16_t b, __amdgpu_buffer_rsrc_t r, uint32_t off)
+    // both codes already packed (Codec::enc2)
+    static __device__ __forceinline__ void st(uint32_t w, __amdgpu_buffer_rsrc_t r, uint32_t off)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(uint32_t(a) | (uint32_t(b) << 16), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(w, r, off, 0, 0);
     }
 };
 
@@ -567,7 +568,10 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            Buf2<T>::st(Cd::enc(v0[q]), Cd::enc(v1[q]), make_rsrc(bq, range), soffP);
+            if constexpr (sizeof(T) == 2)
+                Buf2<T>::st(Cd::enc2(v0[q], v1[q]), make_rsrc(bq, range), soffP);
+            else
+                Buf2<T>::st(v0[q], v1[q], make_rsrc(bq, range), soffP);
             bq += N;
         }
     };

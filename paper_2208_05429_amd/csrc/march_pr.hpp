@@ -387,6 +387,11 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             byz[k] = b | (mv ? 0x80000000u : 0u);
         }
     }
+    // Inside the march a column counts as present through rad alone (rad <= M
+    // only for columns in the domain), and the second pair column's indices
+    // follow from the first: fewer registers live across the march.
+    ci[1] = ci[0] + 1;
+    ci2[1] = ci2[0] + 1;
     // memory offsets: the pair moves as one access keyed on its first column
     // (a pair starts at an even z of an even-length row, so it never wraps)
     const bool pair_loads = rad[0] <= M && gofs[0] >= 0;
@@ -588,7 +593,11 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 v[q] = Cd::dec(LG[q]);
         }
         collide<R, FORCE>(v, omega, Fb[k][0], Fb[k][1], Fb[k][2]);
-        const int sl = ((ci[k] & 1) ? NC / 2 : 0) + (ci[k] >> 1);
+        // (with walls or a force, the slot address is rebuilt per plane rather
+        // than kept live across the march: those variants are short of
+        // registers, and a spilled address reloads behind the plane's loads)
+        int sl = ((ci[k] & 1) ? NC / 2 : 0) + (ci[k] >> 1);
+        if constexpr (WALLS || FORCE) sl = opaque(sl);
         sfor<0, Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + sl] = v[q];
@@ -638,12 +647,12 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[pb][k][c];
         }
         const bool pres = present(xl);
-        if (pres && rad[0] <= M && gofs[0] >= 0)
+        if (pres && rad[0] <= M)
             collide1(std::integral_constant<int, 0>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
-        if (pres && rad[1] <= M && gofs[1] >= 0)
+        if (pres && rad[1] <= M)
             collide1(std::integral_constant<int, 1>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
         load_pair(xl + PF, next_wanted, Lp[pb], Fl1[pb]);
-        if (pres && rad[2] <= M && gofs[2] >= 0)
+        if (pres && rad[2] <= M)
             collide1(std::integral_constant<int, 2>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
         load_ring(xl + PF, next_wanted, Lg[pb], Fl1[pb]);
         __syncthreads();
@@ -657,11 +666,12 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 constexpr int k = decltype(kc)::value;
                 constexpr int PAR = (k == 0) ? (M & 1) : ((k == 1) ? ((M + 1) & 1) : -1);  // parity of ci
                 constexpr int PAR2 = (k == 0) ? 1 : ((k == 1) ? 0 : -1);                 // parity of ci2
-                if (rad[k] <= 1 && gofs[k] >= 0) {
+                if (rad[k] <= 1) {
                     complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], xbd1);
                     if (coll2) {
                         collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
-                        const int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
+                        int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
+                        if constexpr (WALLS || FORCE) sl2 = opaque(sl2);
                         sfor<0, Q>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
                             if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + sl2] = acc1[k][q];
@@ -689,7 +699,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         {
             const int p = xl - M + 1;  // plane the last step collided
             const uint32_t xbd = xb(p - 1), xbn = xb(p), xmn = xm(p);
-            const bool act = rad[0] == 0 && gofs[0] >= 0;
+            const bool act = rad[0] == 0;
             if constexpr (M == 2) {
                 if (act) {
                     complete_s<R, WALLS, 1, NC2, WZ2>(acc2[0], X2, ci2[0], o2[0][1], xbd);

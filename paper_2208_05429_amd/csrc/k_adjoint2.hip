@@ -350,9 +350,17 @@ hipError_t launch_step_adjoint2(int storage, const Geom& g, const void* f_t, con
 {
     switch (storage) {
     case ST_F64: return adjoint2_shape<ST_F64, 8, 8, 256>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    // 12 x 28 tiles: the 16 x 32 frame of tile plus two halo cells fills the
-    // 512 threads exactly (measured 16 % faster than 16 x 16 tiles at 256^3)
-    case ST_F32: return adjoint2_shape<ST_F32, 12, 28, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F32: {
+        // Each tile is one 512-thread workgroup per plane, so the plane takes
+        // the tiling with fewer tiles.  12 x 28 (its 16 x 32 frame of tile
+        // plus two halo cells fills the workgroup exactly; 16 % faster than
+        // 16 x 16 at 256^3) unless its ragged edge tiles make 16 x 16 cheaper
+        // (a 64 x 64 plane: 18 tiles against 16).
+        const long long t1228 = (long long)((g.ny + 11) / 12) * ((g.nz + 27) / 28);
+        const long long t1616 = (long long)((g.ny + 15) / 16) * ((g.nz + 15) / 16);
+        if (t1616 < t1228) return adjoint2_shape<ST_F32, 16, 16, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+        return adjoint2_shape<ST_F32, 12, 28, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    }
     }
     return hipErrorInvalidValue;
 }

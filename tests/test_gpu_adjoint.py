@@ -118,8 +118,9 @@ def test_force_gradient_matches_central_differences_fp64():
 
 
 # Two merged reverse steps (one pass, f_{t+1} recomputed on chip) against two
-# single reverse steps of the oracle.  Shapes span several 12x28 (FP32) or 8x8
-# (FP64) tiles with ragged last tiles and several x segments.
+# single reverse steps of the oracle.  Shapes span several tiles (FP32: 12x28,
+# or 16x16 where that takes fewer tiles, as for the last case; FP64: 8x8) with
+# ragged last tiles and several x segments.
 MERGED_CASES = [
     ((40, 21, 19), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
     ((24, 18, 37), (PERIODIC,) * 6, (0.0, 0.0, 0.0), True),

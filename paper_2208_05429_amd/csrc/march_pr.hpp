@@ -425,7 +425,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     using P2 = typename Buf2<T>::P;
     P2 Lp[PF][Q];  // raw pair loads, PF planes in flight
     T Lg[PF][Q];   // raw ring loads
-    R Fl1[PF][K][3], Fl2[K][3];
+    R Fl1[PF][K][3];
     R acc1[K][Q], nxt1[K][5];  // step 1: pair and ring
     R acc2[2][Q], nxt2[2][5];  // last step of M = 2: pair only
     R o1[K][3], o2[K][3];
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         for (int c = 0; c < 3; ++c) {
 #pragma unroll
             for (int b = 0; b < PF; ++b) Fl1[b][k][c] = R(0);
-            Fl2[k][c] = o1[k][c] = o2[k][c] = R(0);
+            o1[k][c] = o2[k][c] = R(0);
         }
     }
 
@@ -638,14 +638,18 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         const bool next_wanted = i + PF < total;
         const int seen = __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-        // ---- A: step-1 collide of plane xl; loads of plane xl+1 follow each column ----
-        R Fs[K][3];
-        if constexpr (FORCE) {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[pb][k][c];
+        // The force of plane xl-1, which the second step collides in E, is
+        // read again (it was read two planes ago and sits in L2) rather than
+        // kept in registers through two iterations.
+        R Fr[K][3];
+        if constexpr (FORCE && M == 2) {
+            const bool live = i >= M && present(xl - 1);
+            load_force(xl - 1, live, Fr[0], loffPR);
+            load_force(xl - 1, live, Fr[1], loffPR == kOffNone ? kOffNone : loffPR + uint32_t(sizeof(R)));
+            load_force(xl - 1, live, Fr[2], loffGR);
         }
+
+        // ---- A: step-1 collide of plane xl; loads of plane xl+1 follow each column ----
         const bool pres = present(xl);
         if (pres && rad[0] <= M)
             collide1(std::integral_constant<int, 0>{}, X1w, Lp[pb], Lg[pb], Fl1[pb]);
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 if (rad[k] <= 1) {
                     complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], xbd1);
                     if (coll2) {
-                        collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        collide<R, FORCE>(acc1[k], omega, Fr[k][0], Fr[k][1], Fr[k][2]);
                         int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
                         if constexpr (WALLS || FORCE) sl2 = opaque(sl2);
                         sfor<0, Q>([&](auto qc) {
@@ -686,10 +690,6 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                     }
                     deposit_s<R, WALLS, PAR, NC, WZ>(acc1[k], nxt1[k], X1w, ci[k], o1[k][0], o1[k][1], o1[k][2],
                                                      xbn1, byz[k], mlinks(byz[k]) | xmn1, WT, X1w, lane);
-                }
-                if constexpr (FORCE) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) Fl2[k][c] = Fs[k][c];
                 }
             });
             __syncthreads();

@@ -176,6 +176,20 @@ def test_force_channel_fp64_and_fp32():
         assert rel(lat.distributions(), ref) <= 2e-6, scheme
 
 
+def test_force_periodic_pair_layout():
+    # a body force on a periodic lattice with even nz: the pair-and-ring FP32
+    # kernel (several tiles in y and z, a ragged last tile in each)
+    shape = (14, 36, 70)
+    faces = (PERIODIC,) * 6
+    rho0, u0 = _noisy_init(shape, 310)
+    F = wl.normal_field(shape, 1e-4, 311)
+    o = Oracle(shape, 0.7, faces=faces)
+    ref = o.run(o.init(rho0, u0), 9, F)
+    for scheme in SCHEMES:
+        lat, _, _, _ = gpu_run(shape, 0.7, "f32", scheme, faces, rho0=rho0, u0=u0, F=F, steps=9)
+        assert rel(lat.distributions(), ref) <= 2e-6, scheme
+
+
 def test_conservation_sums_match_oracle():
     shape = (20, 37, 45)
     faces, wall_u = CASES[0][1], CASES[0][2]

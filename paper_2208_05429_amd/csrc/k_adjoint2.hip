@@ -70,7 +70,13 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
-    const int wid = blockIdx.x;
+    // Workgroup b runs on XCD b % 8; consecutive work items (z, then y
+    // neighbours) go to the same XCD, so that a tile's halo and the parts of
+    // the cache lines its frame rows share with the next tile are read from
+    // that XCD's L2 rather than again from memory.
+    const int per = gridDim.x >> 3;
+    const int wid = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (wid >= a.items) return;  // padding of the grid
     const int tz = wid % a.ntz, ty = (wid / a.ntz) % a.nty, seg = wid / (a.ntz * a.nty);
     const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
     const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);
@@ -321,16 +327,40 @@ static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, c
     a.gF = gF;
     a.nty = (g.ny + TY - 1) / TY;
     a.ntz = (g.nz + TZ - 1) / TZ;
-    // enough work items to fill the chip twice over, segments of at least 8 planes
-    const int tiles = a.nty * a.ntz;
-    int nseg = (512 + tiles - 1) / tiles;
-    if (nseg > g.nx / 8) nseg = g.nx / 8;
-    if (nseg < 1) nseg = 1;
-    a.seg_len = (g.nx + nseg - 1) / nseg;
-    a.nseg = (g.nx + a.seg_len - 1) / a.seg_len;
-    const dim3 grid(unsigned(tiles * a.nseg));
     const bool walls = g.wall[0] || g.wall[1] || g.wall[2];
     const bool force = F != nullptr;
+    // Work items (tile, x segment) run in waves of `resident` workgroups, and
+    // one item costs its segment length plus the 4 planes that fill its
+    // pipeline.  Take the segment count that minimises waves x (length + 4).
+    static int resident_of[4] = {0, 0, 0, 0};  // per kernel variant (walls, force)
+    int& resident = resident_of[(walls ? 2 : 0) + (force ? 1 : 0)];
+    if (resident == 0) {
+        int dev = 0, cus = 0, per = 0;
+        auto k = walls ? (force ? k_adjoint2<S, TY, TZ, NT, true, true> : k_adjoint2<S, TY, TZ, NT, true, false>)
+                       : (force ? k_adjoint2<S, TY, TZ, NT, false, true> : k_adjoint2<S, TY, TZ, NT, false, false>);
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, NT, 0) == hipSuccess && cus * per > 0)
+            resident = cus * per;
+        else
+            resident = 256;
+    }
+    const long long tiles = (long long)a.nty * a.ntz;
+    long long best = -1;
+    a.nseg = 1;
+    a.seg_len = g.nx;
+    for (int ns = 1; ns <= g.nx; ++ns) {
+        const int len = (g.nx + ns - 1) / ns, n = (g.nx + len - 1) / len;
+        if (n != ns) continue;  // the same split as a smaller count
+        const long long cost = ((tiles * n + resident - 1) / resident) * (len + 4);
+        if (best < 0 || cost < best) {
+            best = cost;
+            a.nseg = n;
+            a.seg_len = len;
+        }
+    }
+    a.items = int(tiles * a.nseg);
+    const dim3 grid(unsigned((a.items + 7) / 8 * 8));
     if (walls) {
         if (force)
             hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, true>), grid, dim3(NT), 0, st, a);

@@ -66,6 +66,7 @@ struct Adj2Args {
     void* lout;        // lambda_t
     void* gF;          // 3N force gradient, accumulated (may be null)
     int nty, ntz, nseg, seg_len;
+    int items;         // tiles x segments; the grid is padded to a multiple of 8
 };
 
 // Launchers; each returns the hipError_t of its launch.

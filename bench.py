@@ -195,17 +195,18 @@ def storage_sweep(size, steps):
     return out
 
 
-def large_run(size, steps):
-    """The large single-copy run: size^3 FP32, periodic, tau 0.55, random-phase
-    Taylor-Green field (seed 4), merged passes in rounds over bands of tile
-    rows when the plane has more tiles than co-resident workgroups."""
+def large_run(size, steps, storage="f32"):
+    """The large single-copy run: size^3 (FP32; FP64 where only one copy fits),
+    periodic, tau 0.55, random-phase Taylor-Green field (seed 4), merged passes
+    in rounds over bands of tile rows when the plane has more tiles than
+    co-resident workgroups."""
     import torch
     from paper_2208_05429_amd import workloads as wl
     from paper_2208_05429_amd.lattice import Lattice
     cfg = wl.TGV_1024
     shape = (size,) * 3
     u0 = wl.taylor_green_3d_device(shape, cfg["u0"], wl.random_phases(cfg["phase_seed"]), "cuda")
-    lat = Lattice(shape, cfg["tau"], "f32", "swap2", u0=u0)
+    lat = Lattice(shape, cfg["tau"], storage, "swap2", u0=u0)
     del u0
     torch.cuda.empty_cache()
     lat.step(2)
@@ -224,10 +225,12 @@ def large_run(size, steps):
     torch.cuda.empty_cache()
     N = size ** 3
     kper = kms[1] / max(kn[1], 1)
-    return {"shape": list(shape), "steps": steps, "MLUPS": round(N * steps / (ms * 1e-3) / 1e6, 1),
+    b = 8 if storage == "f64" else 4
+    return {"shape": list(shape), "storage": storage, "steps": steps,
+            "MLUPS": round(N * steps / (ms * 1e-3) / 1e6, 1),
             "ms_per_step": round(ms / steps, 4), "march_ms_per_pass": round(kper, 4),
-            "achieved_GBs": round(2 * 19 * 4 * N / (kper * 1e-3) / 1e9, 1),
-            "distributions_GB": round(19 * 4 * N / 1e9, 1), "mass_finite": bool(np.isfinite(s).all())}
+            "achieved_GBs": round(2 * 19 * b * N / (kper * 1e-3) / 1e9, 1),
+            "distributions_GB": round(19 * b * N / 1e9, 1), "mass_finite": bool(np.isfinite(s).all())}
 
 
 def main():
@@ -356,6 +359,8 @@ def main():
     if headline and not a.no_large:
         print("[bench] 1024^3 single-copy run", file=sys.stderr, flush=True)
         out["large_1024"] = large_run(1024, 50)
+        print("[bench] 1024^3 FP64 single-copy run (two copies would not fit in HBM)", file=sys.stderr, flush=True)
+        out["large_1024_f64"] = large_run(1024, 10, "f64")
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
         out["adjoint"] = {"workload": adjoint_ratio((128, 64, 64), 200, 20),

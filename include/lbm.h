@@ -140,8 +140,9 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
 
 /* Discrete adjoint of k in {1, 2} forward steps taken from the state f_t_dev
  * (storage type and layout of f, left unchanged): lambda_in_dev holds
- * dL/df_{t+k}; lambda_out_dev receives dL/df_t (distinct buffers, 19N of the
- * arithmetic type); grad_force_dev (3N) accumulates the force gradient of the
+ * dL/df_{t+k}; lambda_out_dev receives dL/df_t (non-overlapping buffers, 19N
+ * of the arithmetic type; every buffer 256-byte aligned, LBM_EINVAL
+ * otherwise); grad_force_dev (3N) accumulates the force gradient of the
  * k steps (required with a force, may be NULL without).  The reverse of the
  * step of Sec. 3: the transposed stream gathers lambda_q from the link's
  * target (the own lambda of the opposite direction on a wall link), then the

@@ -103,10 +103,17 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
         // rounds over bands of tile rows, each band's boundary rows saved first
         const std::string need = "the y-z plane needs " + std::to_string(tiles) +
                                  " marching workgroups, more than can be co-resident (" + std::to_string(cap) + ")";
-        if (!r.pr) return fail(why, LBM_EUNSUPPORTED, need + ", and this kernel layout has no rounds");
+        if (!r.pr && c.storage != LBM_F64)
+            return fail(why, LBM_EUNSUPPORTED, need + ", and the plain 32/16-bit layout (odd nz) has no rounds");
         if (r.ntz > cap) return fail(why, LBM_EUNSUPPORTED, need + ", even for one row of tiles");
-        if (py && c.ny % r.TY != 0)
-            return fail(why, LBM_EUNSUPPORTED, need + "; rounds on a periodic y axis need whole tile rows");
+        // Across the periodic y seam the last row of tiles reads the first
+        // band's saved rows.  The pair-and-ring layout reads them only in the
+        // ring rows above a whole tile; the plain layout in any frame row, but
+        // only the last row of tiles may reach across the seam.
+        if (py && c.ny % r.TY != 0 && (r.pr || c.ny % r.TY < M))
+            return fail(why, LBM_EUNSUPPORTED,
+                        need + (r.pr ? "; rounds on a periodic y axis need whole tile rows"
+                                     : "; rounds on a periodic y axis need a last row of tiles at least as thick as the halo"));
         r.nty_band = cap / r.ntz;
         r.nbands = (r.nty + r.nty_band - 1) / r.nty_band;
         if (c.ny - (r.nbands - 1) * r.nty_band * r.TY < M)
@@ -263,22 +270,14 @@ lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void
 
     size_t off[6], total = 0, sized = 0;
     int cap = kMaxResident;
-    {
-        MarchPlan probe[3];
-        st = layout(*cfg, cap, probe, off, &sized, &g_create_err);  // what lbm_buffer_sizes reported
-        if (st != LBM_OK) {
-            delete ctx;
-            return st;
-        }
+    MarchPlan probe[3];
+    st = layout(*cfg, cap, probe, off, &sized, &g_create_err);  // what lbm_buffer_sizes reported
+    if (st != LBM_OK) {
+        delete ctx;
+        return st;
     }
     if (cfg->scheme != LBM_TWO_ARRAY) {
         // the device may hold fewer marching workgroups than the sizing bound
-        MarchPlan probe[3];
-        st = layout(*cfg, cap, probe, off, &total, &g_create_err);
-        if (st != LBM_OK) {
-            delete ctx;
-            return st;
-        }
         for (int M = 1; M <= 2; ++M) {
             if (probe[M].M == 0) continue;
             const int dc = device_cap(*cfg, probe[M]);
@@ -568,8 +567,16 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
     if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
     if (!f_t_dev || !lambda_in_dev || !lambda_out_dev)
         return fail(&ctx->err, LBM_EINVAL, "f_t, lambda_in and lambda_out are required");
-    if (lambda_in_dev == lambda_out_dev) return fail(&ctx->err, LBM_EINVAL, "lambda_in and lambda_out must differ");
     if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
+    if (!aligned(f_t_dev) || !aligned(lambda_in_dev) || !aligned(lambda_out_dev) ||
+        (grad_force_dev && !aligned(grad_force_dev)))
+        return fail(&ctx->err, LBM_EINVAL, "device buffers must be 256-byte aligned");
+    // lambda_out is written while lambda_in is still read by other workgroups
+    const size_t lam_bytes = size_t(19) * size_t(ctx->g.N) * real_size(ctx->cfg.storage);
+    const char* li = static_cast<const char*>(lambda_in_dev);
+    const char* lo = static_cast<const char*>(lambda_out_dev);
+    if (li < lo + lam_bytes && lo < li + lam_bytes)
+        return fail(&ctx->err, LBM_EINVAL, "lambda_in and lambda_out must not overlap");
     return device_err(ctx,
                       launch_step_adjoint(ctx->cfg.storage, ctx->force != nullptr, k, ctx->g, f_t_dev, ctx->force,
                                           lambda_in_dev, lambda_out_dev, grad_force_dev, ctx->stream),

@@ -153,9 +153,21 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         const int per = gridDim.x >> 3;
         wid = (wid & 7) * per + (wid >> 3);
     }
-    const int tz = wid % a.ntz, ty = (wid / a.ntz) % a.nty, seg = wid / (a.ntz * a.nty);
+    // A round covers the band of tile rows [band_ty0, band_ty0 + nty_band).
+    // This layout runs rounds for FP64 only (the 32-bit storages have the
+    // pair-and-ring layout for that; the band edge code would cost the plain
+    // 32-bit variants registers).
+    constexpr bool ROUNDS = S == ST_F64;
+    const bool banded = a.nty_band < a.nty;
+    const int tz = wid % a.ntz, ty = a.band_ty0 + (wid / a.ntz) % a.nty_band, seg = wid / (a.ntz * a.nty_band);
+    const long long gtile = ((long long)seg * a.nty + ty) * a.ntz + tz;  // progress counter index
     const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
     const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);
+    // Rounds: the band's first (last) row of tiles reads the halo rows below
+    // (above) the band from the saved band boundary rows, when the band there
+    // was already updated this pass (the host passes those copies only then).
+    const T* shell_lo = (banded && ty == a.band_ty0) ? static_cast<const T*>(a.shell_lo) : nullptr;
+    const T* shell_hi = (banded && ty == a.band_ty0 + a.nty_band - 1) ? static_cast<const T*>(a.shell_hi) : nullptr;
     const bool wallx = g.wall[0] != 0;
     const bool has_next = !wallx || seg + 1 < a.nseg;
     const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
@@ -289,10 +301,48 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         }
         const uint32_t range = live ? plane_bytes : 0u;
         const T* bq = base;  // running pointer: nothing per direction stays live across iterations
+        if (!ROUNDS || !(shell_lo || shell_hi) || from_side) {  // (the side planes hold every row at time t)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), loff[k]);
-            bq += qstride;
+            for (int q = 0; q < Q; ++q) {
+                Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), loff[k]);
+                bq += qstride;
+            }
+        } else {
+            // A band edge tile: lanes of the rows beyond the band read the
+            // saved copy ([x][q][row][z], M rows), the others the lattice.
+            // Told apart by the lane's plane offset (row * nz + z) * size: the
+            // M rows below the band sit right under its first row; across the
+            // periodic seam the rows above are rows 0 .. M-1, whose offsets
+            // are those of the copy itself.
+            const long long ss = (long long)M * g.nz;
+            const uint32_t rowb = uint32_t(g.nz) * uint32_t(sizeof(T));
+            const uint32_t lo_first = shell_lo ? uint32_t(a.band_ty0 * TY - M) * rowb : 0u;
+            const uint32_t lo_end = shell_lo ? uint32_t(a.band_ty0 * TY) * rowb : 0u;
+            const uint32_t hi_end = shell_hi ? uint32_t(M) * rowb : 0u;
+            const uint32_t lf = loff[k];
+            const bool in_lo = lf != kOffNone && lf >= lo_first && lf < lo_end;
+            const bool in_hi = lf != kOffNone && lf < hi_end;
+            const uint32_t lofs = (in_lo || in_hi) ? kOffNone : lf;
+            const uint32_t olo = in_lo ? lf - lo_first : kOffNone, ohi = in_hi ? lf : kOffNone;
+            const uint32_t srange = live ? uint32_t(ss) * uint32_t(sizeof(T)) : 0u;
+            const T* blo = shell_lo ? shell_lo + (long long)px * Q * ss : nullptr;
+            const T* bhi = shell_hi ? shell_hi + (long long)px * Q * ss : nullptr;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                T v = Buf<T>::ld(make_rsrc(bq, range), lofs);
+                if (blo) {
+                    const T w = Buf<T>::ld(make_rsrc(blo, srange), olo);
+                    v = in_lo ? w : v;
+                    blo += ss;
+                }
+                if (bhi) {
+                    const T w = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
+                    v = in_hi ? w : v;
+                    bhi += ss;
+                }
+                Lr[k][q] = v;
+                bq += qstride;
+            }
         }
         if constexpr (FORCE) {
             const uint32_t rangeR = live ? uint32_t(PL) * uint32_t(sizeof(R)) : 0u;
@@ -333,6 +383,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         } else {
             yy = wrapi(yy, a.nty);
         }
+        if (yy < a.band_ty0 || yy >= a.band_ty0 + a.nty_band) fkind = 0;  // not in this round
         if (g.wall[2]) {
             if (zz < 0 || zz >= a.ntz) fkind = 0;
         } else {
@@ -464,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             seen = poll_issue();
         }
         __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.flags + (1 + (long long)wid) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) __hip_atomic_store(a.flags + (1 + gtile) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
         if constexpr (M == 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----

@@ -7,7 +7,8 @@
 // lane accesses that cover whole cache lines (a wave reads or writes two
 // rows of 64 floats), and a thread issues 19 pair loads + 19 ring loads + 19
 // pair stores per plane: fewer than the 63 vector-memory operations a wave
-// may have in flight, so no store ever waits for the prefetch.  Ring columns
+// may have in flight, so no store ever waits for the prefetch (with a body
+// force, 18 force loads come on top).  Ring columns
 // (halo of width M) are never stored and never receive the last step, so
 // they carry no last-step pipeline registers.
 //

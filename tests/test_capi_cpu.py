@@ -40,10 +40,12 @@ def _status(cfg):
     (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(storage=capi.LBM_F16_OFS, use_force=True), capi.LBM_EUNSUPPORTED),
     (dict(variant=99), capi.LBM_EUNSUPPORTED),
-    # more tiles than co-resident workgroups: FP64's plain layout has no rounds
-    (dict(shape=(64, 1024, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
+    # more tiles than co-resident workgroups, and odd nz: the plain 32-bit layout has no rounds
+    (dict(shape=(64, 1024, 1023)), capi.LBM_EUNSUPPORTED),
     # rounds on a periodic y axis need whole tile rows (16 rows per tile)
     (dict(shape=(64, 1000, 1024)), capi.LBM_EUNSUPPORTED),
+    # FP64 (12-row tiles) across a periodic y seam: a last tile row thinner than the halo
+    (dict(shape=(64, 1009, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
 ])
 def test_invalid_configs_are_rejected(kw, code):
     assert _status(_cfg(**kw))[0] == code
@@ -71,6 +73,14 @@ def test_rounds_plan_for_large_planes():
     # with walls in y any row count works (the last band may end in a partial tile)
     walls = (0, 0, capi.LBM_WALL, capi.LBM_WALL, 0, 0)
     assert _status(_cfg(shape=(nx, 1000, 1024), faces=walls))[0] == capi.LBM_OK
+    # FP64 (plain layout, 12 x 28 tiles): 86 x 37 tiles, bands of 6 tile rows
+    # (256 // 37), 15 rounds, each band's 2 M boundary rows saved
+    st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024), storage=capi.LBM_F64))
+    assert st == capi.LBM_OK
+    shells = 15 * 2 * 2 * 1024 * nx * 19 * 8
+    assert shells <= wb < shells + 19 * 8 * 1024 * 1024 * 4 + (1 << 24)
+    # a ragged last tile row across the periodic seam at least as thick as the halo
+    assert _status(_cfg(shape=(nx, 1000, 1024), storage=capi.LBM_F64))[0] == capi.LBM_OK
 
 
 def test_null_and_state_errors():

@@ -188,3 +188,15 @@ def test_force_gradient_merged_matches_oracle_adjoint(storage):
         err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
         print(f"{storage} checkpoint {ck}: merged-adjoint gradient error vs oracle adjoint {err:.3e}")
         assert err <= (1e-10 if storage == "f64" else 1e-3)
+
+
+def test_step_adjoint_rejects_overlapping_lambda():
+    shape = (8, 16, 16)
+    lat = Lattice(shape, 0.8, "f32", "swap2")
+    n = 19 * 8 * 16 * 16
+    buf = torch.zeros(2 * n, device="cuda")
+    half = 64 * 19  # lambda_out starts inside lambda_in (256-byte aligned offset)
+    with pytest.raises(capi.LbmError) as ei:
+        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), buf.data_ptr(), buf[half:].data_ptr(), None, 2)
+    assert ei.value.status == capi.LBM_EINVAL
+    lat.close()

@@ -147,6 +147,45 @@ def test_rounds_match_two_array_bitwise(case):
     ref.close()
 
 
+# FP64 runs its plain layout (12 x 28 tiles for two steps, 14 x 30 for one) in
+# rounds; these planes need 612, 666 and 520 of those tiles.  The last case has
+# bands of a single row of tiles, so one workgroup reads saved rows both below
+# its band and across the periodic seam above it.
+FP64_BANDED_CASES = [
+    ((6, 200, 1000), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((5, 210, 1030), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),
+    ((4, 40, 3640), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FP64_BANDED_CASES)))
+def test_rounds_fp64_match_two_array_bitwise(case):
+    shape, faces, wall_u = FP64_BANDED_CASES[case]
+    names = [_NAMES[f] for f in faces]
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, 440 + case)
+    r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 441 + case)), torch.as_tensor(u0)
+    print(f"[gpu] rounds f64 {shape} {names}", flush=True)
+    ref = Lattice(shape, 0.6, "f64", "two_array", names, wall_u, rho0=r0, u0=v0)
+    for scheme in ("swap2", "swap1"):
+        lat = Lattice(shape, 0.6, "f64", scheme, names, wall_u, rho0=r0, u0=v0)
+        lat.f.copy_(ref.f)
+        ref_f0 = ref.f.clone()
+        ref.step(3)
+        lat.step(3)
+        torch.cuda.synchronize()
+        assert torch.equal(lat.f.view(torch.int64), ref.f.view(torch.int64)), scheme
+        dst = torch.empty_like(lat.f)
+        lat.step_into(ref_f0, dst, 2)
+        ref2 = Lattice(shape, 0.6, "f64", "two_array", names, wall_u, f=ref_f0.clone())
+        ref2.step(2)
+        torch.cuda.synchronize()
+        assert torch.equal(dst.view(torch.int64), ref2.f.view(torch.int64)), (scheme, "into")
+        ref2.close()
+        lat.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case", [0, 1])
 def test_rounds_16bit_in_place_matches_out_of_place(storage, case):
@@ -214,6 +253,39 @@ def test_tgv1024_fp32_merged_rounds_sampled_cells():
         assert np.abs(g - ref).max() <= 2e-7, c
     assert abs(s1[0] - s0[0]) <= 1e-9 * s0[0]
     assert np.abs(s1[1:] - s0[1:]).max() <= 1e-9 * s0[0]
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
+def test_tgv1024_fp64_merged_rounds_sampled_cells():
+    # 1024^3 in FP64: 163 GB of distributions, which fit the 288 GB of HBM only
+    # as a single copy (two arrays would need 326 GB); 15 rounds of bands of six
+    # 12-row tile rows per merged pass, a ragged last tile row across the seam
+    cfg = wl.TGV_1024
+    shape, tau, n = cfg["shape"], cfg["tau"], 4
+    ph = wl.random_phases(cfg["phase_seed"])
+    print(f"[gpu] 1024^3 f64 swap2 rounds, {n} steps", flush=True)
+    u0 = wl.taylor_green_3d_device(shape, cfg["u0"], ph, "cuda")
+    lat = Lattice(shape, tau, "f64", "swap2", u0=u0)
+    del u0
+    torch.cuda.empty_cache()
+    s0 = lat.sums()
+    lat.step(n)
+    torch.cuda.synchronize()
+    s1 = lat.sums()
+    # band seams (rows 71/72, 143/144, 1007/1008), the ragged last tile row
+    # (1020-1023) and its periodic seam, tile seams in z (28-column tiles), the x wrap
+    cells = [(0, 71, 0), (1, 72, 27), (1023, 143, 28), (512, 144, 1023), (7, 1007, 500), (100, 1008, 511),
+             (5, 1019, 3), (3, 1020, 55), (1023, 1023, 1), (0, 0, 1022)] + wl.sample_cells(shape, 8, 12)
+    got = gpu_cells(lat, cells)
+    ufn = lambda ix, iy, iz: wl.taylor_green_3d_at(shape, cfg["u0"], ph, ix, iy, iz)  # noqa: E731
+    faces = (PERIODIC,) * 6
+    for c, g in zip(cells, got):
+        ref = oracle_center(None, ufn, shape, faces, (0, 0, 0), tau, c, n)
+        assert np.abs(g - ref).max() <= 1e-13, c
+    assert abs(s1[0] - s0[0]) <= 1e-12 * s0[0]
+    assert np.abs(s1[1:] - s0[1:]).max() <= 1e-12 * s0[0]
     lat.close()
     del lat
     torch.cuda.empty_cache()

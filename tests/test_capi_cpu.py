@@ -33,6 +33,7 @@ def _status(cfg):
     (dict(tau=0.5), capi.LBM_EINVAL),
     (dict(tau=float("nan")), capi.LBM_EINVAL),
     (dict(shape=(0, 4, 4)), capi.LBM_EINVAL),
+    (dict(shape=(1, 65536, 32768)), capi.LBM_EINVAL),  # ny*nz must stay below 2^31
     (dict(storage=7), capi.LBM_EINVAL),
     (dict(scheme=5), capi.LBM_EINVAL),
     (dict(faces=(capi.LBM_WALL, capi.LBM_PERIODIC, 0, 0, 0, 0)), capi.LBM_EINVAL),

@@ -55,6 +55,32 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+// Work item -> (tile z, tile row within the band, x segment).  Items of a
+// segment go stripe by stripe, each stripe about 512 cells wide in z and
+// row-major inside, so that the 32 consecutive items one XCD runs (after the
+// XCD remap) form a compact block of tiles whose halos its L2 shares: four
+// tile rows of eight 64-wide tiles rather than two rows of a 1024-wide plane.
+template <int TZ>
+__device__ __forceinline__ void tile_of_item(int item, int nty, int ntz, int& tz, int& ty, int& seg)
+{
+    constexpr int WANT = (512 / TZ) > 0 ? 512 / TZ : 1;
+    const int bz = ntz < WANT ? ntz : WANT;
+    const int run = nty * ntz;
+    seg = item / run;
+    const int r = item - seg * run;
+    const int full = ntz / bz, per_stripe = nty * bz;
+    const int s = r / per_stripe;
+    if (s < full) {
+        const int l = r - s * per_stripe;
+        ty = l / bz;
+        tz = s * bz + (l - (l / bz) * bz);
+    } else {  // the narrower last stripe
+        const int w = ntz - full * bz, l = r - full * per_stripe;
+        ty = l / w;
+        tz = full * bz + (l - (l / w) * w);
+    }
+}
+
 // The two halves of one level's exchange for one column.  The level has just
 // collided plane p: the post-collision values of the column-moving
 // directions are in X (16 rows of `stride` columns; this column at index ci,
@@ -159,7 +185,9 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     // 32-bit variants registers).
     constexpr bool ROUNDS = S == ST_F64;
     const bool banded = a.nty_band < a.nty;
-    const int tz = wid % a.ntz, ty = a.band_ty0 + (wid / a.ntz) % a.nty_band, seg = wid / (a.ntz * a.nty_band);
+    int tz, ty, seg;
+    tile_of_item<TZ>(wid, a.nty_band, a.ntz, tz, ty, seg);
+    ty += a.band_ty0;
     const long long gtile = ((long long)seg * a.nty + ty) * a.ntz + tz;  // progress counter index
     const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
     const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);

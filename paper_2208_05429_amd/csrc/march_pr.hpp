@@ -301,7 +301,9 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         wid = (wid & 7) * per + (wid >> 3);
     }
     const bool banded = a.nty_band < a.nty;
-    const int tz = wid % a.ntz, ty = a.band_ty0 + (wid / a.ntz) % a.nty_band, seg = wid / (a.ntz * a.nty_band);
+    int tz, ty, seg;
+    tile_of_item<TZ>(wid, a.nty_band, a.ntz, tz, ty, seg);
+    ty += a.band_ty0;
     const long long gtile = ((long long)seg * a.nty + ty) * a.ntz + tz;  // progress counter index
     const int s = seg * a.seg_len, e = min(s + a.seg_len, g.nx);
     const int TYe = min(TY, g.ny - ty * TY), TZe = min(TZ, g.nz - tz * TZ);

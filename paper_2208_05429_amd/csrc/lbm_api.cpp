@@ -139,6 +139,7 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     r.seg_len = seg_len;
     r.blocks = tiles_run * nseg;
     r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
+    r.cap = cap;
     r.side_bytes = size_t(nseg) * size_t(M) * 19u * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
     r.shell_bytes = r.nbands > 1 ? size_t(r.nbands) * 2u * size_t(M) * size_t(c.nz) * size_t(c.nx) * 19u *
                                        elem_size(c.storage)
@@ -385,7 +386,11 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
         a.nty_band = std::min(p.nty_band, p.nty - a.band_ty0);
         a.shell_lo = (inplace && b > 0) ? shell + (size_t(2 * (b - 1) + 1)) * part : nullptr;
         a.shell_hi = (inplace && p.nbands > 1 && b == p.nbands - 1 && py) ? shell : nullptr;
-        pb.blocks = a.nty_band * p.ntz * p.nseg;
+        // work items of the round; the grid is padded with idle workgroups to
+        // a multiple of 8 (when they still fit) so that the XCD remap applies
+        a.items = a.nty_band * p.ntz * p.nseg;
+        const int padded = (a.items + 7) / 8 * 8;
+        pb.blocks = padded <= p.cap ? padded : a.items;
         pb.xcd_remap = (pb.blocks % 8 == 0) ? 1 : 0;
         a.xcd_remap = pb.xcd_remap;
         switch (ctx->cfg.storage) {

@@ -29,6 +29,7 @@ struct MarchPlan {
     int nseg = 0, seg_len = 0;   // x segments
     int ry = 1, rz = 1;          // neighbourhood radius (in tiles) of the hazard check
     int blocks = 0;              // nty*ntz*nseg work items, all co-resident
+    int cap = 0;                 // co-resident workgroups the plan was made for
     int xcd_remap = 0;           // map consecutive work items onto one XCD
     size_t side_bytes = 0;       // side planes: nseg * M planes * 19 values
     int flag_stride = 1;         // ints between two progress counters
@@ -56,6 +57,7 @@ struct MarchArgs {
     int band_ty0, nty_band;
     const void* shell_lo;  // rows below the band: [x][q][M][nz] copy, or null (read f)
     const void* shell_hi;  // rows above the band, likewise
+    int items;             // work items of this launch; the grid may be padded to a multiple of 8
 };
 
 // One merged two-step adjoint pass (out of place).

@@ -179,6 +179,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         const int per = gridDim.x >> 3;
         wid = (wid & 7) * per + (wid >> 3);
     }
+    if (wid >= a.items) return;  // padding of the grid (uniform per workgroup, before any barrier)
     // A round covers the band of tile rows [band_ty0, band_ty0 + nty_band).
     // This layout runs rounds for FP64 only (the 32-bit storages have the
     // pair-and-ring layout for that; the band edge code would cost the plain

@@ -300,6 +300,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         const int per = gridDim.x >> 3;
         wid = (wid & 7) * per + (wid >> 3);
     }
+    if (wid >= a.items) return;  // padding of the grid (uniform per workgroup, before any barrier)
     const bool banded = a.nty_band < a.nty;
     int tz, ty, seg;
     tile_of_item<TZ>(wid, a.nty_band, a.ntz, tz, ty, seg);

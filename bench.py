@@ -237,7 +237,7 @@ def large_run(size, steps, storage="f32"):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); multi-GPU runs are not part of this build",
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     if a.steps % 2 or a.warmup % 2:

@@ -186,6 +186,29 @@ def test_rounds_fp64_match_two_array_bitwise(case):
     ref.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_rounds_with_force_match_two_array_bitwise(storage):
+    # a body force in rounds (the force is read at each cell's own position,
+    # also for halo rows taken from the saved band boundary rows)
+    shape = (6, 272, 1024) if storage == "f32" else (6, 200, 1000)
+    faces = (PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC)
+    names = [_NAMES[f] for f in faces]
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, 460)
+    r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 461)), torch.as_tensor(u0)
+    F = torch.as_tensor(wl.normal_field(shape, 1e-4, 462))
+    print(f"[gpu] rounds with force {storage} {shape}", flush=True)
+    ref = Lattice(shape, 0.7, storage, "two_array", names, force=F, rho0=r0, u0=v0)
+    lat = Lattice(shape, 0.7, storage, "swap2", names, force=F, rho0=r0, u0=v0)
+    ref.step(3)
+    lat.step(3)
+    torch.cuda.synchronize()
+    view = torch.int32 if storage == "f32" else torch.int64
+    assert torch.equal(lat.f.view(view), ref.f.view(view))
+    lat.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case", [0, 1])
 def test_rounds_16bit_in_place_matches_out_of_place(storage, case):

@@ -329,6 +329,9 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "conservation": {"mass": sums[0], "momentum": list(sums[1:])},
     }
+    if traffic:
+        # measured HBM bytes (rocprofv3, calibrated) over the same launch time
+        out["roofline"]["measured_gbs"] = round(traffic / (avg_kernel_ms * 1e-3) / 1e9, 1)
     lat.close()
     del lat
     torch.cuda.empty_cache()

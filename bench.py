@@ -44,7 +44,7 @@ def parse():
                          "Taylor-Green (tau 0.55, seed 4) built on the device, for 1024^3")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=24.0, help="target length of the oracle sample (the estimate from a short timing runs long, so the sample lands near 10-20 s)")
     ap.add_argument("--copy-probe", type=int, default=1 << 31, metavar="BYTES",
                     help="device-to-device copy of BYTES bytes: achievable read+write rate, counter calibration")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")

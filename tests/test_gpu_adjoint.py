@@ -200,3 +200,36 @@ def test_step_adjoint_rejects_overlapping_lambda():
         capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), buf.data_ptr(), buf[half:].data_ptr(), None, 2)
     assert ei.value.status == capi.LBM_EINVAL
     lat.close()
+
+
+def test_merged_adjoint_at_256_cubed_matches_two_single_steps():
+    # the bench's bandwidth-bound adjoint workload: 256^3 channel with a body
+    # force, FP32, in the launch configuration it is timed in (12 x 28 tiles,
+    # eight x segments, XCD-ordered work items); the merged kernel against two
+    # launches of the single-step adjoint, an independent gather formulation
+    # (measured: bit-identical; the bound allows for a different rounding order)
+    shape = (256, 256, 256)
+    names = ("periodic", "periodic", "wall", "wall", "wall", "wall")
+    F = torch.as_tensor(wl.normal_field(shape, 1e-4, 70), dtype=torch.float32)
+    print("[gpu] merged adjoint 256^3 f32 channel with force", flush=True)
+    lat = Lattice(shape, 0.8, "f32", "swap2", names, force=F)
+    lat.step(4)
+    f_t = lat.f.clone()
+    lat.step(1)
+    f_t1 = lat.f.clone()
+    g = torch.Generator(device="cuda").manual_seed(71)
+    lam2 = torch.randn((19,) + shape, device="cuda", generator=g)
+    lout = torch.empty_like(lam2)
+    gF = torch.zeros((3,) + shape, device="cuda")
+    capi.lbm_step_adjoint(lat.ctx, f_t.data_ptr(), lam2.data_ptr(), lout.data_ptr(), gF.data_ptr(), 2)
+    mid = torch.empty_like(lam2)
+    ref = torch.empty_like(lam2)
+    gR = torch.zeros_like(gF)
+    capi.lbm_step_adjoint(lat.ctx, f_t1.data_ptr(), lam2.data_ptr(), mid.data_ptr(), gR.data_ptr(), 1)
+    capi.lbm_step_adjoint(lat.ctx, f_t.data_ptr(), mid.data_ptr(), ref.data_ptr(), gR.data_ptr(), 1)
+    torch.cuda.synchronize()
+    e = ((lout - ref).abs().max() / ref.abs().max()).item()
+    eg = ((gF - gR).abs().max() / gR.abs().max()).item()
+    print(f"merged vs single steps at 256^3: lambda {e:.3e}, force gradient {eg:.3e}")
+    assert e <= 2e-5 and eg <= 2e-5, (e, eg)
+    lat.close()

@@ -6,7 +6,8 @@ two-array kernel, itself held to 1e-12 of the CPU oracle by the parity tests
 on the cells [0, 64)^3: err(X) = max|X - X_ref| / max|X_ref| for rho - 1 and
 for u as one vector field.  FP16/BF16 storage has no exact reference (every
 store rounds): these bounds are the measured orders with a safety factor, not
-a parity claim.
+a parity claim.  The 16-bit forms are pinned instead by the error bound of a
+single rounding (the last test).
 """
 import numpy as np
 import pytest
@@ -56,3 +57,51 @@ def test_reduced_precision_error_vs_fp64_on_crop():
         if st == "f32":
             assert er <= 1e-3, er
     assert errs["f32"][1] < errs["f16"][1] < errs["bf16"][1]
+
+
+# ---------------------------------------------------------------------------
+# Rounding bound of one 16-bit store.  From a state whose stored offsets are
+# exact 16-bit values, one pass (one step, or two merged steps whose
+# intermediate stays in FP32) computes in FP32 and rounds each offset g once
+# to nearest even, so every stored value lies within half a 16-bit ulp of the
+# exact FP64 result (the oracle run from the same decoded state), plus the
+# FP32 arithmetic error of the collision.  A pin of the 16-bit forms against
+# the oracle by the error bound of their one rounding.
+
+def _half_ulp(x, storage):
+    a = np.abs(x)
+    if storage == "f16":
+        e = np.floor(np.log2(np.maximum(a, 2.0 ** -14)))  # subnormals: fixed spacing 2^-24
+        return 0.5 * 2.0 ** (e - 10)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -126)))
+    return 0.5 * 2.0 ** (e - 7)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("scheme,steps", [("swap1", 1), ("swap2", 2), ("two_array", 1)])
+def test_one_16bit_store_is_within_half_an_ulp_of_the_oracle(storage, scheme, steps):
+    from oracle import MOVING_WALL, WALL, Oracle
+    from paper_2208_05429_amd.lattice import lattice_weights
+    shape = (12, 20, 70)
+    faces = (WALL, WALL, WALL, MOVING_WALL, WALL, WALL)
+    names = ("wall", "wall", "wall", "moving", "wall", "wall")
+    wall_u = (0.05, 0.0, 0.01)
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, 480)
+    rho0 = wl.random_density(shape, 0.01, 481)
+    print(f"[gpu] one {storage} store, {scheme}, {steps} step(s)", flush=True)
+    lat = Lattice(shape, 0.7, storage, scheme, names, wall_u, rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0))
+    f0 = lat.distributions()  # the decoded 16-bit state: exact in FP64
+    lat.step(steps)
+    torch.cuda.synchronize()
+    w = lattice_weights()[:, None, None, None]
+    g_gpu = lat.distributions() - w
+    o = Oracle(shape, 0.7, faces=faces, wall_u=wall_u)
+    g_ref = o.run(np.ascontiguousarray(f0), steps) - w
+    err = np.abs(g_gpu - g_ref)
+    # (the binade of the larger of the two: rounding up across a power of two)
+    bound = _half_ulp(np.maximum(np.abs(g_ref), np.abs(g_gpu)), storage) * (1 + 1e-3) + 2e-7
+    worst = float((err / bound).max())
+    print(f"{storage} {scheme}: max |g - g_ref| = {err.max():.3e}, max err/bound = {worst:.3f}")
+    assert worst <= 1.0, worst
+    lat.close()

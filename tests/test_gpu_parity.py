@@ -3,8 +3,8 @@ CPU oracle on the same seeded inputs.
 
 Error metric (per field, as for the Taylor-Green workload): max |X_gpu - X_ref|
 / max |X_ref| with u taken as one vector field.  Bars: FP64 <= 1e-12, FP32
-<= 2e-6 after 100 steps; 16-bit storage is reported against loose bounds
-(parity unpinned: only the storage rounding bounds it).
+<= 2e-6 after 100 steps; 16-bit storage over many steps is reported against
+loose bounds (its pin is the half-ulp bound of one store, test_gpu_precision.py).
 """
 import math
 
@@ -79,7 +79,7 @@ def test_tgv32_fp32_matches_oracle(tgv32_ref, scheme):
 
 @pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 2e-2)])
 def test_tgv32_16bit_storage_error_is_bounded(tgv32_ref, storage, bound):
-    # parity unpinned: storage rounding of f - w bounds this, no exact reference
+    # 100 steps of 16-bit rounding of f - w: a loose bound on the accumulated error
     cfg = wl.TGV_32
     rho0, u0, rho_ref, u_ref, _ = tgv32_ref
     for scheme in ("swap1", "swap2"):

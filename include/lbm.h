@@ -133,7 +133,10 @@ lbm_status lbm_step_into(lbm_ctx* ctx, const void* f_src, void* f_dst, int32_t k
  * unorm_dev: N; each may be NULL.  If sums_host is not NULL it receives
  * { sum rho, sum_q c_x f, sum_q c_y f, sum_q c_z f } over all cells (the
  * populations' mass and momentum, accumulated in double on the device in a
- * fixed order), and the call waits for them. */
+ * fixed order), and the call waits for them.  That call also reports
+ * LBM_EDEVICE if any in-place pass of this context so far gave up waiting
+ * for a neighbouring workgroup (a bounded wait; the state is then not to be
+ * trusted, and the report stays set for the life of the context). */
 lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double* unorm_dev, double* sums_host);
 
 /* Discrete adjoint, seed: given dL/du of the velocity field of the state

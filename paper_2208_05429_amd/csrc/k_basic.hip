@@ -100,8 +100,21 @@ __global__ __launch_bounds__(256) void k_prepass(Geom g, const T* __restrict__ f
         const int plane = (b * seg_len + j) % g.nx;
         side[t] = f[q * g.N + (long long)plane * g.PL + o];
     }
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < nflags; t += (long long)gridDim.x * 256)
+    // progress counters 1 .. nflags-1; word 0, the timeout report, is left as
+    // it is: it stays set once any pass of the context has timed out
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x + 1; t < nflags; t += (long long)gridDim.x * 256)
         flags[t * fstride] = 0;
+}
+
+__global__ __launch_bounds__(64) void k_clear_word(int* w)
+{
+    if (threadIdx.x == 0) w[0] = 0;
+}
+
+hipError_t launch_clear_word(int* w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, s, w);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------

@@ -26,9 +26,6 @@ struct lbm_ctx {
     std::string err;
     MarchPlan plan[3];  // indexed by M
     size_t off_partials = 0, off_sums = 0, off_second = 0, off_flags = 0, off_side = 0, off_shell = 0;
-    // the timeout word is meaningful once an in-place pass (whose prepass clears
-    // it) has run: the work buffer arrives uninitialised
-    bool guarded_pass = false;
     // measurement hook: event pairs around update-kernel launches
     bool timing = false;
     std::vector<hipEvent_t> ev;  // 2 per recorded launch, reused
@@ -305,6 +302,17 @@ lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void
     ctx->off_flags = off[3];
     ctx->off_side = off[4];
     ctx->off_shell = off[5];
+    if (cfg->scheme != LBM_TWO_ARRAY) {
+        // the timeout report of the in-place passes starts clear (the work
+        // buffer arrives uninitialised) and is never cleared by a pass
+        st = device_err(ctx, launch_clear_word(reinterpret_cast<int*>(ctx->work + ctx->off_flags), ctx->stream),
+                        "timeout word clear");
+        if (st != LBM_OK) {
+            g_create_err = ctx->err;
+            delete ctx;
+            return st;
+        }
+    }
     *out = ctx;
     return LBM_OK;
 }
@@ -350,7 +358,6 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
         lbm_status st = device_err(ctx, launch_prepass(ctx->cfg.storage, ctx->g, p, src, side, flags, ctx->stream),
                                    "prepass launch");
         if (st != LBM_OK) return st;
-        ctx->guarded_pass = true;
         if (p.nbands > 1) {
             st = device_err(ctx, launch_shells(ctx->cfg.storage, ctx->g, p, p.TY, src, shell, ctx->stream),
                             "band boundary copy launch");
@@ -536,7 +543,7 @@ lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double*
     st = device_err(ctx, hipMemcpyAsync(sums_host, sums, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
                     "sums copy");
     int timeout = 0;
-    if (st == LBM_OK && ctx->cfg.scheme != LBM_TWO_ARRAY && ctx->guarded_pass)
+    if (st == LBM_OK && ctx->cfg.scheme != LBM_TWO_ARRAY)
         st = device_err(ctx,
                         hipMemcpyAsync(&timeout, ctx->work + ctx->off_flags, sizeof(int), hipMemcpyDeviceToHost,
                                        ctx->stream),

@@ -81,6 +81,7 @@ hipError_t launch_prepass(int storage, const Geom& g, const MarchPlan& p, const 
                           hipStream_t s);
 hipError_t launch_shells(int storage, const Geom& g, const MarchPlan& p, int TY, const void* f, void* shell,
                          hipStream_t s);
+hipError_t launch_clear_word(int* w, hipStream_t s);  // w[0] = 0, as a kernel (safe inside a captured graph)
 
 constexpr int SUM_BLOCKS = 1024;  // fixed grid of the reduction: deterministic order
 hipError_t launch_macro(int storage, bool force, const Geom& g, const void* f, const void* F, double* rho, double* u,

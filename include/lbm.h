@@ -174,6 +174,14 @@ lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Rebind the context to another stream (a hipStream_t as void*). */
+/* Test hook for the failure path of the in-place hazard wait: with enable != 0
+ * every wait of later in-place passes requires progress no neighbour can
+ * reach and gives up after a few polls, as if a neighbouring workgroup had
+ * stalled.  The passes still run to the end with every access in bounds, but
+ * their results are not to be trusted, and lbm_macroscopic with sums reports
+ * the time-out (LBM_EDEVICE) from then on.  Not for production use. */
+lbm_status lbm_test_force_wait_timeout(lbm_ctx* ctx, int32_t enable);
+
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
 
 /* Message of the last failed call on ctx (or of the last failed lbm_init /

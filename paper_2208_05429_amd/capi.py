@@ -57,6 +57,7 @@ def lib():
         L.lbm_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32]
         L.lbm_set_stream.argtypes = [_vp, _vp]
         L.lbm_set_kernel_timing.argtypes = [_vp, ctypes.c_int32]
+        L.lbm_test_force_wait_timeout.argtypes = [_vp, ctypes.c_int32]
         L.lbm_kernel_time.argtypes = [_vp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.lbm_last_error.argtypes = [_vp]
         L.lbm_last_error.restype = ctypes.c_char_p
@@ -64,7 +65,7 @@ def lib():
         L.lbm_destroy.restype = None
         for name in ("lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_step_into", "lbm_macroscopic",
                      "lbm_macro_adjoint", "lbm_step_adjoint", "lbm_set_stream", "lbm_set_kernel_timing",
-                     "lbm_kernel_time"):
+                     "lbm_kernel_time", "lbm_test_force_wait_timeout"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -145,6 +146,10 @@ def lbm_set_stream(ctx, stream):
 
 def lbm_set_kernel_timing(ctx, enable):
     _check(lib().lbm_set_kernel_timing(ctx, 1 if enable else 0), ctx)
+
+
+def lbm_test_force_wait_timeout(ctx, enable):
+    _check(lib().lbm_test_force_wait_timeout(ctx, 1 if enable else 0), ctx)
 
 
 def lbm_kernel_time(ctx):

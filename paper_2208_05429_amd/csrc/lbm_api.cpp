@@ -26,6 +26,7 @@ struct lbm_ctx {
     std::string err;
     MarchPlan plan[3];  // indexed by M
     size_t off_partials = 0, off_sums = 0, off_second = 0, off_flags = 0, off_side = 0, off_shell = 0;
+    bool force_wait_timeout = false;  // test hook: every hazard wait gives up
     // measurement hook: event pairs around update-kernel launches
     bool timing = false;
     std::vector<hipEvent_t> ev;  // 2 per recorded launch, reused
@@ -380,6 +381,8 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
     a.rz = p.rz;
     a.xcd_remap = p.xcd_remap;
     a.fstride = p.flag_stride;
+    a.spin_limit = ctx->force_wait_timeout ? 4 : (1 << 22);
+    a.need_bias = ctx->force_wait_timeout ? (1 << 29) : 0;
     const bool walls = ctx->g.wall[0] || ctx->g.wall[1] || ctx->g.wall[2];
     const bool force = ctx->force != nullptr;
     const size_t part = size_t(ctx->g.nx) * 19u * size_t(M) * size_t(ctx->g.nz) * elem_size(ctx->cfg.storage);
@@ -625,6 +628,13 @@ lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches)
     }
     ctx->ev_used = 0;
     ctx->ev_steps.clear();
+    return LBM_OK;
+}
+
+lbm_status lbm_test_force_wait_timeout(lbm_ctx* ctx, int32_t enable)
+{
+    if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
+    ctx->force_wait_timeout = enable != 0;
     return LBM_OK;
 }
 

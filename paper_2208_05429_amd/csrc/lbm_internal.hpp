@@ -58,6 +58,10 @@ struct MarchArgs {
     const void* shell_lo;  // rows below the band: [x][q][M][nz] copy, or null (read f)
     const void* shell_hi;  // rows above the band, likewise
     int items;             // work items of this launch; the grid may be padded to a multiple of 8
+    // bounded hazard wait: polls before giving up (and reporting a time-out),
+    // and a bias added to the progress a wait requires (0; a test hook sets an
+    // unreachable one so that every wait gives up)
+    int spin_limit, need_bias;
 };
 
 // One merged two-step adjoint pass (out of place).

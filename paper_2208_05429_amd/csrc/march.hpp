@@ -431,11 +431,11 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     };
     auto poll_issue = [&]() -> int { return __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
     auto poll_finish = [&](int seen, int i, int r) {
-        const int need = poll_need(i, r);
+        const int need = poll_need(i, r) + a.need_bias;
         if (__all(seen >= need)) return;
         // bounded wait: a timeout is recorded in flags[0] and the march goes on
         bool ok = seen >= need;
-        for (int spin = 0; spin < (1 << 22) && !__all(ok); ++spin) {
+        for (int spin = 0; spin < a.spin_limit && !__all(ok); ++spin) {
             __builtin_amdgcn_s_sleep(2);
             if (!ok) ok = __hip_atomic_load(flp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
         }

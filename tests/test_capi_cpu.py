@@ -103,4 +103,5 @@ def test_null_and_state_errors():
     assert L.lbm_macroscopic(None, None, None, None, None) == capi.LBM_ESTATE
     assert L.lbm_step_adjoint(None, None, None, None, None, 1) == capi.LBM_ESTATE
     assert L.lbm_set_stream(None, None) == capi.LBM_ESTATE
+    assert L.lbm_test_force_wait_timeout(None, 1) == capi.LBM_ESTATE
     L.lbm_destroy(None)

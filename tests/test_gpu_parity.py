@@ -14,6 +14,7 @@ import torch
 
 import oracle
 from oracle import MOVING_WALL, PERIODIC, WALL, Oracle
+from paper_2208_05429_amd import capi
 from paper_2208_05429_amd import workloads as wl
 from paper_2208_05429_amd.lattice import Lattice, real_dtype
 
@@ -269,3 +270,30 @@ def test_degenerate_lattices_match_oracle(case):
             assert rel(lat.distributions(), ref) <= 1e-12, (scheme, steps)
             lat32, _, _, _ = gpu_run(shape, 0.7, "f32", scheme, faces, wall_u, rho0, u0, steps=steps)
             assert rel(lat32.distributions(), ref) <= 2e-6, (scheme, steps)
+
+
+@pytest.mark.parametrize("shape", [(40, 70, 46), (40, 70, 45)])  # pair-and-ring and plain layouts
+def test_a_wait_that_gives_up_is_reported_and_stays_reported(shape):
+    # failure path of the in-place hazard wait, forced from the host: every
+    # wait requires unreachable progress and gives up after a few polls; the
+    # passes still complete (accesses stay in bounds) and the time-out shows
+    # in lbm_macroscopic, also after later, normal passes
+    lat = Lattice(shape, 0.6, "f32", "swap2")
+    lat.step(2)
+    assert np.isfinite(lat.sums()).all()  # a normal pass reports nothing
+    capi.lbm_test_force_wait_timeout(lat.ctx, True)
+    print("[gpu] forced hazard-wait time-outs", flush=True)
+    lat.step(4)
+    with pytest.raises(capi.LbmError) as ei:
+        lat.sums()
+    assert ei.value.status == capi.LBM_EDEVICE and "timed out" in str(ei.value)
+    capi.lbm_test_force_wait_timeout(lat.ctx, False)
+    lat.step(2)
+    with pytest.raises(capi.LbmError):
+        lat.sums()
+    lat.close()
+    # a new context starts with a clear report
+    lat = Lattice(shape, 0.6, "f32", "swap2")
+    lat.step(2)
+    assert np.isfinite(lat.sums()).all()
+    lat.close()

@@ -186,6 +186,27 @@ def test_rounds_fp64_match_two_array_bitwise(case):
     ref.close()
 
 
+@pytest.mark.parametrize("variant", [2, 4])  # 32 x 32 pair-and-ring tiles; loads two planes ahead
+def test_rounds_of_other_kernel_shapes_match_two_array_bitwise(variant):
+    shape, faces, wall_u = (6, 544, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)
+    if variant == 4:
+        shape = BANDED_CASES[1][0]
+        faces, wall_u = BANDED_CASES[1][1], BANDED_CASES[1][2]
+    names = [_NAMES[f] for f in faces]
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, 470 + variant)
+    r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 471 + variant)), torch.as_tensor(u0)
+    print(f"[gpu] rounds, kernel variant {variant}, {shape} {names}", flush=True)
+    ref = Lattice(shape, 0.6, "f32", "two_array", names, wall_u, rho0=r0, u0=v0)
+    lat = Lattice(shape, 0.6, "f32", "swap2", names, wall_u, rho0=r0, u0=v0, variant=variant)
+    ref.step(3)
+    lat.step(3)
+    torch.cuda.synchronize()
+    assert torch.equal(lat.f.view(torch.int32), ref.f.view(torch.int32))
+    lat.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_rounds_with_force_match_two_array_bitwise(storage):
     # a body force in rounds (the force is read at each cell's own position,

@@ -108,7 +108,9 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
     """Backward (recompute + merged adjoint) time per step over merged forward
     time per step, for L = sum |u_T - u*|^2 on a channel (periodic x, walls in
     y and z, tau 0.8) under a per-cell force N(0, 1e-12) (seed 1); u* from a
-    forward run under a hidden force (seed 2)."""
+    forward run under a hidden force (seed 2).  Also: the checkpointing
+    forward of the autograd function per step, and the merged adjoint kernel
+    alone against one merged forward pass."""
     import torch
     from paper_2208_05429_amd import workloads as wl
     from paper_2208_05429_amd.adjoint import ForceAdjoint
@@ -123,7 +125,7 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
     lat.close()
     lat = Lattice(shape, 0.8, "f32", "swap2", faces, force=F, f=f0.clone())
     spec = dict(shape=shape, tau=0.8, storage="f32", faces=faces, steps=steps, checkpoint=checkpoint, merged=True)
-    fwd, bwd = [], []
+    fwd, bwd, ckf = [], [], []
     for r in range(reps + 1):
         lat.f.copy_(f0)
         torch.cuda.synchronize()
@@ -133,7 +135,10 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
         e1.record()
         torch.cuda.synchronize()
         Fp = F.clone().requires_grad_(True)
+        c0, c1 = _events()
+        c0.record()
         u = ForceAdjoint.apply(Fp, f0, spec)
+        c1.record()
         L = ((u - ut.float()) ** 2).sum()
         torch.cuda.synchronize()
         b0, b1 = _events()
@@ -144,6 +149,7 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
         if r:  # the first round warms up
             fwd.append(e0.elapsed_time(e1))
             bwd.append(b0.elapsed_time(b1))
+            ckf.append(c0.elapsed_time(c1))
     # the adjoint kernel alone, one merged reverse pass, against one merged forward pass
     lam = torch.randn((19,) + tuple(shape), device="cuda")
     lout = torch.empty_like(lam)
@@ -163,10 +169,11 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
     m1.record()
     torch.cuda.synchronize()
     lat.close()
-    fw, bw = float(np.median(fwd)) / steps, float(np.median(bwd)) / steps
+    fw, bw, cf = float(np.median(fwd)) / steps, float(np.median(bwd)) / steps, float(np.median(ckf)) / steps
     ka, kf = a0.elapsed_time(a1) / (2 * n), m0.elapsed_time(m1) / (2 * n)
     return {"shape": list(shape), "steps": steps, "checkpoint": checkpoint, "forward_ms_per_step": round(fw, 5),
             "backward_ms_per_step": round(bw, 5), "ratio": round(bw / fw, 3),
+            "checkpointing_forward_ms_per_step": round(cf, 5),
             "adjoint_kernel_ms_per_step": round(ka, 5), "forward_kernel_ms_per_step": round(kf, 5),
             "kernel_ratio": round(ka / kf, 3)}
 
@@ -368,7 +375,9 @@ def main():
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
         out["adjoint"] = {"workload": adjoint_ratio((128, 64, 64), 200, 20),
-                          "bandwidth_bound": adjoint_ratio((256, 256, 256), 40, 20, reps=2)}
+                          "bandwidth_bound": adjoint_ratio((256, 256, 256), 40, 20, reps=2),
+                          # every other state kept (20 x 1.3 GB): no recompute in the backward
+                          "bandwidth_bound_every_other_state": adjoint_ratio((256, 256, 256), 40, 2, reps=2)}
     if not a.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)

@@ -2,9 +2,10 @@
 body force, through the library's discrete adjoint (argument marshalling only).
 
 Forward: T time steps from f0 under the Guo force F, keeping the state every
-`checkpoint` steps.  Backward: lambda_T = dL/df_T from dL/du (lbm_macro_adjoint,
-which also adds the direct dL/dF), then for each checkpoint interval in
-reverse: recompute the states the reverse steps start from (lbm_step_into,
+`checkpoint` steps; each kept state is written by the out-of-place pass that
+ends its interval, so keeping it costs no copy.  Backward: lambda_T = dL/df_T
+from dL/du (lbm_macro_adjoint, which also adds the direct dL/dF), then for
+each checkpoint interval in reverse: recompute the states the reverse steps start from (lbm_step_into,
 out of place, so no state is ever copied), and run the adjoint backwards
 (lbm_step_adjoint), accumulating dL/dF.  With spec["merged"] the reverse
 steps go two at a time (the adjoint of the merged pass, f_{t+1} recomputed on
@@ -31,14 +32,17 @@ class ForceAdjoint(torch.autograd.Function):
         shape, storage = tuple(spec["shape"]), spec["storage"]
         steps, k = int(spec["steps"]), int(spec["checkpoint"])
         lat = Lattice(shape, spec["tau"], storage, spec.get("scheme", "swap2"), spec["faces"],
-                      spec.get("wall_u", (0.0, 0.0, 0.0)), force=F.detach(), f=f0.detach().clone())
-        ckpts = []
+                      spec.get("wall_u", (0.0, 0.0, 0.0)), force=F.detach(),
+                      f=torch.empty(f0.shape, dtype=f0.dtype, device=f0.device))
+        ckpts = [f0.detach().clone(memory_format=torch.contiguous_format)]
         t = 0
         while t < steps:
-            ckpts.append(lat.f.clone())
             n = min(k, steps - t)
-            lat.step(n)
             t += n
+            dst = torch.empty_like(lat.f) if t < steps else None  # None: the final state, in lat.f
+            forward_interval(lat, ckpts[-1], dst, n)
+            if dst is not None:
+                ckpts.append(dst)
         _, u, _, _ = lat.macroscopic(want=("u",))
         ctx.lat, ctx.ckpts, ctx.spec = lat, ckpts, spec
         ctx.save_for_backward(F)
@@ -76,6 +80,26 @@ class ForceAdjoint(torch.autograd.Function):
                 lam, lam2 = lam2, lam
         F, = ctx.saved_tensors
         return gF.to(F.dtype), None, None
+
+
+def forward_interval(lat, src, dst, n):
+    """n >= 1 steps from the state src into dst, or into lat.f (the lattice's
+    own buffer) when dst is None.  src is left as it is and no state is copied:
+    the first pass reads src, the last one writes dst, and the passes between
+    run in place in lat.f (an out-of-place pass moves the same bytes as an
+    in-place one)."""
+    if dst is None:
+        lat.step_into(src, lat.f, min(n, 2))
+        if n > 2:
+            lat.step(n - 2)
+    elif n <= 2:
+        lat.step_into(src, dst, n)
+    else:
+        last = 2 if n >= 4 else 1
+        lat.step_into(src, lat.f, 2)
+        if n - 2 - last:
+            lat.step(n - 2 - last)
+        lat.step_into(lat.f, dst, last)
 
 
 def reverse_schedule(n, merged):

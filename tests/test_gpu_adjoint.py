@@ -190,6 +190,28 @@ def test_force_gradient_merged_matches_oracle_adjoint(storage):
         assert err <= (1e-10 if storage == "f64" else 1e-3)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("merged,intervals", [(True, (2, 4, 6, 12)), (False, (1, 5, 12))])
+def test_force_gradient_does_not_depend_on_the_checkpoint_interval(storage, merged, intervals):
+    # The reverse passes group the steps the same way for all these intervals
+    # (merged: even ones), and a state reached in place, out of place or
+    # recomputed is the same to the bit (FP32 and FP64), so keeping every
+    # (other) state, or only the first, gives the same gradient bitwise.
+    shape, steps = (16, 12, 10), 12
+    o, f0, F, ut, f0_dev = _channel_problem(shape, steps, storage)
+    Fd, utd = torch.as_tensor(F, device="cuda"), torch.as_tensor(ut, device="cuda")
+    out = {}
+    for ck in intervals:
+        spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=ck, merged=merged)
+        out[ck] = force_gradient(Fd, f0_dev, spec, utd)
+    L0, g0 = out[intervals[0]]
+    assert torch.isfinite(g0).all() and g0.abs().max() > 0
+    for ck in intervals[1:]:
+        L, g = out[ck]
+        assert L == L0, ck
+        assert torch.equal(g, g0), (ck, (g - g0).abs().max().item())
+
+
 def test_step_adjoint_rejects_overlapping_lambda():
     shape = (8, 16, 16)
     lat = Lattice(shape, 0.8, "f32", "swap2")

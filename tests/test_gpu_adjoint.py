@@ -212,6 +212,25 @@ def test_force_gradient_does_not_depend_on_the_checkpoint_interval(storage, merg
         assert torch.equal(g, g0), (ck, (g - g0).abs().max().item())
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_force_gradient_does_not_depend_on_the_forward_scheme(storage):
+    # the three schemes reach the same states to the bit, so the checkpointed
+    # forward and the recompute give the same gradient whichever one runs them
+    shape, steps = (16, 12, 10), 12
+    o, f0, F, ut, f0_dev = _channel_problem(shape, steps, storage)
+    Fd, utd = torch.as_tensor(F, device="cuda"), torch.as_tensor(ut, device="cuda")
+    out = {}
+    for scheme in ("swap2", "swap1", "two_array"):
+        spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=5, merged=True,
+                    scheme=scheme)
+        out[scheme] = force_gradient(Fd, f0_dev, spec, utd)
+    L0, g0 = out["swap2"]
+    for scheme in ("swap1", "two_array"):
+        L, g = out[scheme]
+        assert L == L0, scheme
+        assert torch.equal(g, g0), (scheme, (g - g0).abs().max().item())
+
+
 def test_step_adjoint_rejects_overlapping_lambda():
     shape = (8, 16, 16)
     lat = Lattice(shape, 0.8, "f32", "swap2")

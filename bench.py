@@ -95,8 +95,31 @@ def cpu_baseline(target_s):
     o.run(f, steps)
     el = time.perf_counter() - t0
     n = int(np.prod(shape))
+    # the same oracle on one thread, over a quarter of the time
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.run(f, 2)
+    dt1 = (time.perf_counter() - t0) / 2
+    steps1 = max(2, int(target_s / 4 / max(dt1, 1e-6)))
+    t0 = time.perf_counter()
+    o.run(f, steps1)
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     return {"value": round(n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"64^3 periodic Taylor-Green+noise, tau=0.6, {steps} steps, FP64 two-array, {el:.1f} s"}
+            "sample": f"64^3 periodic Taylor-Green+noise, tau=0.6, {steps} steps, FP64 two-array, {el:.1f} s",
+            "value_1_thread": round(n * steps1 / el1 / 1e6, 3), "sample_1_thread": f"{steps1} steps, {el1:.1f} s",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _events():

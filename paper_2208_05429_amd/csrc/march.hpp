@@ -356,21 +356,48 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             const uint32_t srange = live ? uint32_t(ss) * uint32_t(sizeof(T)) : 0u;
             const T* blo = shell_lo ? shell_lo + (long long)px * Q * ss : nullptr;
             const T* bhi = shell_hi ? shell_hi + (long long)px * Q * ss : nullptr;
+            // The M rows beyond a band edge fill whole waves in the usual
+            // geometry, so a wave mostly reads one source: it then loads from
+            // it alone and the loads stay in flight across the iteration.  A
+            // wave that mixes sources loads all of them and keeps, per lane,
+            // the one its row needs, which waits for the loads at once.
+            const bool lat = lf != kOffNone && !in_lo && !in_hi;
+            const bool any_lat = __any(lat), any_lo = __any(in_lo), any_hi = __any(in_hi);
+            if (!any_lo && !any_hi) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                T v = Buf<T>::ld(make_rsrc(bq, range), lofs);
-                if (blo) {
-                    const T w = Buf<T>::ld(make_rsrc(blo, srange), olo);
-                    v = in_lo ? w : v;
+                for (int q = 0; q < Q; ++q) {
+                    Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), lf);
+                    bq += qstride;
+                }
+            } else if (!any_lat && !any_hi) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    Lr[k][q] = Buf<T>::ld(make_rsrc(blo, srange), olo);
                     blo += ss;
                 }
-                if (bhi) {
-                    const T w = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
-                    v = in_hi ? w : v;
+            } else if (!any_lat && !any_lo) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    Lr[k][q] = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
                     bhi += ss;
                 }
-                Lr[k][q] = v;
-                bq += qstride;
+            } else {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    T v = Buf<T>::ld(make_rsrc(bq, range), lofs);
+                    if (blo) {
+                        const T w = Buf<T>::ld(make_rsrc(blo, srange), olo);
+                        v = in_lo ? w : v;
+                        blo += ss;
+                    }
+                    if (bhi) {
+                        const T w = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
+                        v = in_hi ? w : v;
+                        bhi += ss;
+                    }
+                    Lr[k][q] = v;
+                    bq += qstride;
+                }
             }
         }
         if constexpr (FORCE) {

@@ -38,10 +38,13 @@ def parse():
     ap.add_argument("--scheme", default="swap2", choices=["swap2", "swap1", "two_array"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "cavity", "large"],
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "cavity", "large", "channel"],
                     help="tgv: the periodic Taylor-Green + noise workload (tau 0.6); cavity: lid-driven cavity "
                          "(tau 0.52, five walls, +y lid at 0.05 along x, rest state); large: periodic random-phase "
-                         "Taylor-Green (tau 0.55, seed 4) built on the device, for 1024^3")
+                         "Taylor-Green (tau 0.55, seed 4) built on the device, for 1024^3; channel: the adjoint's "
+                         "channel (periodic x, walls in y and z, tau 0.8, per-cell force N(0, 1e-12) seed 1, rest "
+                         "state)")
+    ap.add_argument("--shape", default=None, metavar="NXxNYxNZ", help="a lattice of this shape instead of --size cubed")
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="target length of the oracle sample (the estimate from a short timing runs long, so the sample lands near 10-20 s)")
@@ -277,14 +280,18 @@ def main():
     from paper_2208_05429_amd import workloads as wl
     from paper_2208_05429_amd.lattice import Lattice
 
-    shape = (a.size,) * 3
+    shape = (a.size,) * 3 if a.shape is None else tuple(int(v) for v in a.shape.lower().split("x"))
+    if len(shape) != 3 or min(shape) < 1:
+        print(f"--shape must be NXxNYxNZ (got {a.shape})", file=sys.stderr)
+        sys.exit(2)
+    sname = f"{a.size}^3" if a.shape is None else "x".join(str(v) for v in shape)
     N = int(np.prod(shape))
     print(f"[bench] building {shape} {a.storage} {a.scheme} {a.workload}", file=sys.stderr, flush=True)
     if a.workload == "cavity":
         tau = wl.CAVITY_256["tau"]
         lat = Lattice(shape, tau, a.storage, a.scheme, ("wall", "wall", "wall", "moving", "wall", "wall"),
                       (wl.CAVITY_256["lid_u"], 0.0, 0.0), variant=a.variant)
-        wdesc = (f"{a.size}^3 lid-driven cavity D3Q19 BGK tau={tau}, halfway bounce-back on 5 walls, +y lid "
+        wdesc = (f"{sname} lid-driven cavity D3Q19 BGK tau={tau}, halfway bounce-back on 5 walls, +y lid "
                  f"u=({wl.CAVITY_256['lid_u']},0,0), rest state, {a.storage} storage")
     elif a.workload == "large":
         cfg = wl.TGV_1024
@@ -292,8 +299,16 @@ def main():
         u0_dev = wl.taylor_green_3d_device(shape, cfg["u0"], wl.random_phases(cfg["phase_seed"]), "cuda")
         lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
         del u0_dev
-        wdesc = (f"{a.size}^3 periodic D3Q19 BGK tau={tau}, random-phase Taylor-Green u0={cfg['u0']} (seed "
+        wdesc = (f"{sname} periodic D3Q19 BGK tau={tau}, random-phase Taylor-Green u0={cfg['u0']} (seed "
                  f"{cfg['phase_seed']}), {a.storage} storage")
+    elif a.workload == "channel":
+        tau = 0.8
+        F = torch.from_numpy(wl.normal_field(shape, 1e-6, 1)).to(torch.float64 if a.storage == "f64" else torch.float32)
+        lat = Lattice(shape, tau, a.storage, a.scheme, ("periodic", "periodic", "wall", "wall", "wall", "wall"),
+                      force=F.cuda(), variant=a.variant)
+        del F
+        wdesc = (f"{sname} channel D3Q19 BGK tau={tau}, periodic x, bounce-back walls in y and z, per-cell body "
+                 f"force N(0, 1e-12) (seed 1), rest state, {a.storage} storage")
     else:
         tau = wl.TGV_512["tau"]
         _, u0 = wl.tgv_512_fields(shape)
@@ -301,7 +316,7 @@ def main():
         del u0
         lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
         del u0_dev
-        wdesc = (f"{a.size}^3 periodic D3Q19 BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
+        wdesc = (f"{sname} periodic D3Q19 BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
                  f"(seed 20805429), {a.storage} storage")
     torch.cuda.empty_cache()
     print(f"[bench] warmup {a.warmup} steps", file=sys.stderr, flush=True)
@@ -333,6 +348,8 @@ def main():
     alg_bytes = 2 * 19 * s * N  # one read and one write of the single copy per launch
     achieved = alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
     kernel_key = (f"march_M{M}_{a.storage}_{a.size}" if a.scheme != "two_array" else f"two_array_{a.storage}_{a.size}")
+    if a.shape is not None:
+        kernel_key += "_" + sname
     if a.workload != "tgv":
         kernel_key += "_" + a.workload
     traffic = traffic_entry(kernel_key)
@@ -385,7 +402,7 @@ def main():
         out["copy_probe"] = {"bytes": a.copy_probe, "ms": round(best, 4)}
         del src, dst
         torch.cuda.empty_cache()
-    headline = a.storage == "f32" and a.scheme == "swap2" and a.workload == "tgv"
+    headline = a.storage == "f32" and a.scheme == "swap2" and a.workload == "tgv" and a.shape is None
     if headline and not a.no_storage_sweep:
         print("[bench] FP16/BF16 storage runs", file=sys.stderr, flush=True)
         sw = storage_sweep(a.size, 40)

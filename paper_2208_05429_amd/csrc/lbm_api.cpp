@@ -101,8 +101,6 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
         // rounds over bands of tile rows, each band's boundary rows saved first
         const std::string need = "the y-z plane needs " + std::to_string(tiles) +
                                  " marching workgroups, more than can be co-resident (" + std::to_string(cap) + ")";
-        if (!r.pr && c.storage != LBM_F64)
-            return fail(why, LBM_EUNSUPPORTED, need + ", and the plain 32/16-bit layout (odd nz) has no rounds");
         if (r.ntz > cap) return fail(why, LBM_EUNSUPPORTED, need + ", even for one row of tiles");
         // Across the periodic y seam the last row of tiles reads the first
         // band's saved rows.  The pair-and-ring layout reads them only in the

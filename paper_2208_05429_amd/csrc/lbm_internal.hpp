@@ -35,8 +35,7 @@ struct MarchPlan {
     int flag_stride = 1;         // ints between two progress counters
     size_t flag_bytes = 0;       // timeout word + one counter per work item
     // y-z planes with more tiles than can be co-resident run as rounds over
-    // bands of nty_band tile rows (the pair-and-ring kernel, and the plain
-    // layout for FP64)
+    // bands of nty_band tile rows (both kernel layouts)
     int nbands = 1, nty_band = 0;
     size_t shell_bytes = 0;      // the M boundary rows of every band, all x: nbands * 2 * M rows
 };

@@ -155,7 +155,7 @@ __device__ __forceinline__ void deposit(R (&acc)[Q], R (&nxt)[5], const R* __res
     });
 }
 
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
 __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 {
     using Cd = Codec<S>;
@@ -181,10 +181,9 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     }
     if (wid >= a.items) return;  // padding of the grid (uniform per workgroup, before any barrier)
     // A round covers the band of tile rows [band_ty0, band_ty0 + nty_band).
-    // This layout runs rounds for FP64 only (the 32-bit storages have the
-    // pair-and-ring layout for that; the band edge code would cost the plain
-    // 32-bit variants registers).
-    constexpr bool ROUNDS = S == ST_F64;
+    // ROUNDS compiles the band edge code in; the 32- and 16-bit storages
+    // launch that build only for planes that run in rounds, since it costs
+    // their variants registers.
     const bool banded = a.nty_band < a.nty;
     int tz, ty, seg;
     tile_of_item<TZ>(wid, a.nty_band, a.ntz, tz, ty, seg);
@@ -610,23 +609,23 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
 // Launch of one compiled shape.  Cooperative launch guarantees co-residency
 // of all work items (required by the progress-counter protocol).
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
 hipError_t launch_march_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
 {
-    auto kern = k_march<S, M, TY, TZ, NT, WALLS, FORCE>;
+    auto kern = k_march<S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>;
     MarchArgs arg = a;
     void* params[] = {&arg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks), dim3(NT), params, 0, st);
 }
 
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
 int max_blocks_shape()
 {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<S, M, TY, TZ, NT, WALLS, FORCE>, NT, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>, NT,
+                                                     0) != hipSuccess)
         return 0;
     return per_cu * cus;
 }

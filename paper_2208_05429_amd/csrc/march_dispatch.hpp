@@ -14,29 +14,50 @@ struct Shape {
     {
         return p.pr == 0 && p.pf == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
     }
-    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    // FP64 always runs the build with the band edge code; the other storages
+    // only for planes that run in rounds
+    template <bool R>
+    static hipError_t launch_r(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
     {
         if constexpr (ALLOW_FORCE) {
             if (force)
-                return walls ? launch_march_shape<S, M, TY, TZ, NT, true, true>(p, a, s)
-                             : launch_march_shape<S, M, TY, TZ, NT, false, true>(p, a, s);
+                return walls ? launch_march_shape<S, M, TY, TZ, NT, true, true, R>(p, a, s)
+                             : launch_march_shape<S, M, TY, TZ, NT, false, true, R>(p, a, s);
         } else {
             if (force) return hipErrorInvalidValue;
         }
-        return walls ? launch_march_shape<S, M, TY, TZ, NT, true, false>(p, a, s)
-                     : launch_march_shape<S, M, TY, TZ, NT, false, false>(p, a, s);
+        return walls ? launch_march_shape<S, M, TY, TZ, NT, true, false, R>(p, a, s)
+                     : launch_march_shape<S, M, TY, TZ, NT, false, false, R>(p, a, s);
     }
-    static int max_blocks(bool walls, bool force)
+    template <bool R>
+    static int max_blocks_r(bool walls, bool force)
     {
         if constexpr (ALLOW_FORCE) {
             if (force)
-                return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, true>()
-                             : max_blocks_shape<S, M, TY, TZ, NT, false, true>();
+                return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, true, R>()
+                             : max_blocks_shape<S, M, TY, TZ, NT, false, true, R>();
         } else {
             if (force) return 0;
         }
-        return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, false>()
-                     : max_blocks_shape<S, M, TY, TZ, NT, false, false>();
+        return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, false, R>()
+                     : max_blocks_shape<S, M, TY, TZ, NT, false, false, R>();
+    }
+    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        if constexpr (S == ST_F64) {
+            return launch_r<true>(walls, force, p, a, s);
+        } else {
+            return p.nbands > 1 ? launch_r<true>(walls, force, p, a, s) : launch_r<false>(walls, force, p, a, s);
+        }
+    }
+    static int max_blocks(bool walls, bool force)
+    {
+        if constexpr (S == ST_F64) {
+            return max_blocks_r<true>(walls, force);
+        } else {
+            const int a = max_blocks_r<false>(walls, force), b = max_blocks_r<true>(walls, force);
+            return a < b ? a : b;
+        }
     }
 };
 

@@ -41,8 +41,8 @@ def _status(cfg):
     (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(storage=capi.LBM_F16_OFS, use_force=True), capi.LBM_EUNSUPPORTED),
     (dict(variant=99), capi.LBM_EUNSUPPORTED),
-    # more tiles than co-resident workgroups, and odd nz: the plain 32-bit layout has no rounds
-    (dict(shape=(64, 1024, 1023)), capi.LBM_EUNSUPPORTED),
+    # rounds with odd nz (plain layout) across a periodic y seam: a last tile row thinner than the halo
+    (dict(shape=(64, 1009, 1023)), capi.LBM_EUNSUPPORTED),
     # rounds on a periodic y axis need whole tile rows (16 rows per tile)
     (dict(shape=(64, 1000, 1024)), capi.LBM_EUNSUPPORTED),
     # FP64 (12-row tiles) across a periodic y seam: a last tile row thinner than the halo
@@ -82,6 +82,12 @@ def test_rounds_plan_for_large_planes():
     assert shells <= wb < shells + 19 * 8 * 1024 * 1024 * 4 + (1 << 24)
     # a ragged last tile row across the periodic seam at least as thick as the halo
     assert _status(_cfg(shape=(nx, 1000, 1024), storage=capi.LBM_F64))[0] == capi.LBM_OK
+    # odd nz: the plain layout (16 x 64 tiles) runs the same four rounds, in every storage
+    for storage, s in ((capi.LBM_F32, 4), (capi.LBM_BF16_OFS, 2), (capi.LBM_F16_OFS, 2)):
+        st, fb, wb = _status(_cfg(shape=(nx, 1024, 1023), storage=storage))
+        assert st == capi.LBM_OK
+        shells = 4 * 2 * 2 * 1023 * nx * 19 * s
+        assert shells <= wb < shells + 19 * s * 1024 * 1023 * 4 + (1 << 24)
 
 
 def test_null_and_state_errors():

@@ -92,10 +92,10 @@ typedef struct {
  * output may be NULL.  In-place schemes march y-z tiles with one workgroup
  * each; a plane with more tiles than the device holds workgroups at once runs
  * in rounds over bands of tile rows, whose boundary rows the work buffer then
- * also holds.  LBM_EUNSUPPORTED, with the reason, where that is not built:
- * rounds across a periodic y axis whose last tile row is ragged (32/16-bit
- * storage with even nz) or thinner than the halo (FP64, and 32/16-bit storage
- * with odd nz). */
+ * also holds (across a periodic y axis a ragged last tile row then takes the
+ * one-column-per-thread layout).  LBM_EUNSUPPORTED, with the reason, where
+ * that is not built: rounds across a periodic y axis whose last tile row is
+ * thinner than the halo. */
 lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work_bytes);
 
 /* Create a context and set f to the equilibrium of (rho0, u0) (Sec. 5.1: one

@@ -58,7 +58,7 @@ lbm_status fail(std::string* where, lbm_status st, const std::string& msg)
     return st;
 }
 
-bool march_shape_of(int storage, int M, int variant, int nz, MarchPlan* r)
+bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPlan* r)
 {
     const ShapeEntry* tab = storage == LBM_F64 ? kShapesF64 : kShapesF32;
     const int n = storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
@@ -66,8 +66,9 @@ bool march_shape_of(int storage, int M, int variant, int nz, MarchPlan* r)
     int idx = 2 * variant + (M == 2 ? 0 : 1);
     if (variant < 0 || idx >= n || tab[idx].M != M) return false;
     // pairs of z-adjacent cells need an even row length: take the plain-layout
-    // entry of the same tile (or else the first plain entry) for odd nz
-    if (tab[idx].pr && (nz % 2) != 0) {
+    // entry of the same tile (or else the first plain entry) for odd nz, and
+    // where the caller asks for the plain layout
+    if (tab[idx].pr && ((nz % 2) != 0 || plain)) {
         int alt = -1;
         for (int j = 0; j < n && alt < 0; ++j)
             if (!tab[j].pr && tab[j].M == M && tab[j].TY == tab[idx].TY && tab[j].TZ == tab[idx].TZ) alt = j;
@@ -89,12 +90,23 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
 {
     MarchPlan r;
     r.M = M;
-    if (!march_shape_of(c.storage, M, c.variant, c.nz, &r))
+    if (!march_shape_of(c.storage, M, c.variant, c.nz, false, &r))
         return fail(why, LBM_EUNSUPPORTED, "no compiled marching kernel for this storage/variant");
+    const bool py = c.face[2] == LBM_PERIODIC, pz = c.face[4] == LBM_PERIODIC;
     r.nty = (c.ny + r.TY - 1) / r.TY;
     r.ntz = (c.nz + r.TZ - 1) / r.TZ;
+    if (r.pr && r.nty * r.ntz > cap && py && c.ny % r.TY != 0) {
+        // The pair-and-ring layout reads saved rows across a periodic y seam
+        // only above a whole tile row; the plain layout of the same tile also
+        // takes a ragged last row (if it is at least as thick as the halo).
+        MarchPlan q = r;
+        if (march_shape_of(c.storage, M, c.variant, c.nz, true, &q)) {
+            r = q;
+            r.nty = (c.ny + r.TY - 1) / r.TY;
+            r.ntz = (c.nz + r.TZ - 1) / r.TZ;
+        }
+    }
     const int tiles = r.nty * r.ntz;
-    const bool py = c.face[2] == LBM_PERIODIC, pz = c.face[4] == LBM_PERIODIC;
     r.nbands = 1;
     r.nty_band = r.nty;
     if (tiles > cap) {

@@ -116,6 +116,8 @@ BANDED_CASES = [
     # odd nz: the plain layout (one column per thread, three columns each) in rounds
     ((5, 304, 1001), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),                           # 19 x 16 tiles, 2 rounds
     ((5, 282, 999), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),  # ragged, lid on +y
+    # even nz, periodic y with a ragged last tile row (8 of 16 rows): the plain layout of the same tile
+    ((5, 296, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
 ]
 _NAMES = {PERIODIC: "periodic", WALL: "wall", MOVING_WALL: "moving"}
 
@@ -237,7 +239,7 @@ def test_rounds_with_force_match_two_array_bitwise(storage):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("case", [0, 1, 3, 4])
+@pytest.mark.parametrize("case", [0, 1, 3, 4, 5])
 def test_rounds_16bit_in_place_matches_out_of_place(storage, case):
     # 16-bit offset storage in rounds: the saved band boundary rows are raw
     # 16-bit codes.  The merged pass rounds to 16 bits once per two steps (the

@@ -355,11 +355,13 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             const uint32_t srange = live ? uint32_t(ss) * uint32_t(sizeof(T)) : 0u;
             const T* blo = shell_lo ? shell_lo + (long long)px * Q * ss : nullptr;
             const T* bhi = shell_hi ? shell_hi + (long long)px * Q * ss : nullptr;
-            // The M rows beyond a band edge fill whole waves in the usual
-            // geometry, so a wave mostly reads one source: it then loads from
-            // it alone and the loads stay in flight across the iteration.  A
-            // wave that mixes sources loads all of them and keeps, per lane,
-            // the one its row needs, which waits for the loads at once.
+            // Every path issues exactly one load per direction and nothing
+            // that reads the loaded values, so the loads stay in flight across
+            // the iteration and the compiler's count of outstanding loads is
+            // the same on every path (a path that issued more, or picked a
+            // value per lane after loading, made the whole march wait for the
+            // next plane's loads: rounds 3x slower).  A wave whose lanes all
+            // read one source loads through that source's buffer descriptor.
             const bool lat = lf != kOffNone && !in_lo && !in_hi;
             const bool any_lat = __any(lat), any_lo = __any(in_lo), any_hi = __any(in_hi);
             if (!any_lo && !any_hi) {
@@ -381,22 +383,19 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     bhi += ss;
                 }
             } else {
+                // A wave that mixes sources: one global load per lane and
+                // direction from the address of its own source, so the wave
+                // issues the same loads as on the other paths.  A lane with
+                // nothing to load reads its plane's first value, which it
+                // never uses.
+                using GT = const T __attribute__((address_space(1)));
+                const uintptr_t ulo = reinterpret_cast<uintptr_t>(blo), uhi = reinterpret_cast<uintptr_t>(bhi);
+                const uintptr_t ula = reinterpret_cast<uintptr_t>(bq);
+                const uintptr_t dlo = uintptr_t(ss) * sizeof(T), dla = uintptr_t(qstride) * sizeof(T);
+                const uintptr_t own = in_lo ? ulo + olo : (in_hi ? uhi + ohi : ula + (lf == kOffNone ? 0u : lf));
+                const uintptr_t step = (in_lo || in_hi) ? dlo : dla;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    T v = Buf<T>::ld(make_rsrc(bq, range), lofs);
-                    if (blo) {
-                        const T w = Buf<T>::ld(make_rsrc(blo, srange), olo);
-                        v = in_lo ? w : v;
-                        blo += ss;
-                    }
-                    if (bhi) {
-                        const T w = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
-                        v = in_hi ? w : v;
-                        bhi += ss;
-                    }
-                    Lr[k][q] = v;
-                    bq += qstride;
-                }
+                for (int q = 0; q < Q; ++q) Lr[k][q] = *reinterpret_cast<GT*>(own + uintptr_t(q) * step);
             }
         }
         if constexpr (FORCE) {

@@ -93,9 +93,10 @@ typedef struct {
  * each; a plane with more tiles than the device holds workgroups at once runs
  * in rounds over bands of tile rows, whose boundary rows the work buffer then
  * also holds (across a periodic y axis a ragged last tile row then takes the
- * one-column-per-thread layout).  LBM_EUNSUPPORTED, with the reason, where
- * that is not built: rounds across a periodic y axis whose last tile row is
- * thinner than the halo. */
+ * one-column-per-thread layout, with another tile height where the row would
+ * be thinner than the halo).  LBM_EUNSUPPORTED, with the reason, where that is
+ * not built: rounds across a periodic y axis whose last tile row is thinner
+ * than the halo for every tile height built. */
 lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work_bytes);
 
 /* Create a context and set f to the equilibrium of (rho0, u0) (Sec. 5.1: one

@@ -85,6 +85,27 @@ bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPl
     return true;
 }
 
+// A plain-layout shape for M steps whose last tile row across a periodic y
+// seam is at least as thick as the halo (or whole), in table order.
+bool plain_shape_for_seam(int storage, int M, int ny, MarchPlan* r)
+{
+    const ShapeEntry* tab = storage == LBM_F64 ? kShapesF64 : kShapesF32;
+    const int n = storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
+                                     : int(sizeof(kShapesF32) / sizeof(ShapeEntry));
+    for (int j = 0; j < n; ++j) {
+        if (tab[j].pr || tab[j].M != M) continue;
+        const int rem = ny % tab[j].TY;
+        if (rem != 0 && rem < M) continue;
+        r->TY = tab[j].TY;
+        r->TZ = tab[j].TZ;
+        r->NT = tab[j].NT;
+        r->pr = 0;
+        r->pf = tab[j].pf;
+        return true;
+    }
+    return false;
+}
+
 // Tiles, segments and the hazard neighbourhood of one marching pass.
 lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::string* why)
 {
@@ -101,6 +122,16 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
         // takes a ragged last row (if it is at least as thick as the halo).
         MarchPlan q = r;
         if (march_shape_of(c.storage, M, c.variant, c.nz, true, &q)) {
+            r = q;
+            r.nty = (c.ny + r.TY - 1) / r.TY;
+            r.ntz = (c.nz + r.TZ - 1) / r.TZ;
+        }
+    }
+    if (!r.pr && r.nty * r.ntz > cap && py && c.ny % r.TY != 0 && c.ny % r.TY < M) {
+        // that last row would be thinner than the halo: another plain tile
+        // height may leave a thick enough one
+        MarchPlan q = r;
+        if (plain_shape_for_seam(c.storage, M, c.ny, &q)) {
             r = q;
             r.nty = (c.ny + r.TY - 1) / r.TY;
             r.ntz = (c.nz + r.TZ - 1) / r.TZ;

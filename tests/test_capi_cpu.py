@@ -41,10 +41,11 @@ def _status(cfg):
     (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(storage=capi.LBM_F16_OFS, use_force=True), capi.LBM_EUNSUPPORTED),
     (dict(variant=99), capi.LBM_EUNSUPPORTED),
-    # rounds with odd nz (plain layout) across a periodic y seam: a last tile row thinner than the halo
-    (dict(shape=(64, 1009, 1023)), capi.LBM_EUNSUPPORTED),
-    # rounds across a periodic y seam: a last tile row (16-row tiles) thinner than the halo
-    (dict(shape=(64, 1009, 1024)), capi.LBM_EUNSUPPORTED),
+    # rounds across a periodic y seam: a last tile row thinner than the halo for
+    # every tile height built (16 and 32 rows)
+    (dict(shape=(64, 1025, 1024)), capi.LBM_EUNSUPPORTED),
+    # the same with odd nz (plain layout only)
+    (dict(shape=(64, 1025, 1023)), capi.LBM_EUNSUPPORTED),
     # FP64 (12-row tiles) across a periodic y seam: a last tile row thinner than the halo
     (dict(shape=(64, 1009, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
 ])
@@ -74,8 +75,10 @@ def test_rounds_plan_for_large_planes():
     # with walls in y any row count works (the last band may end in a partial tile)
     walls = (0, 0, capi.LBM_WALL, capi.LBM_WALL, 0, 0)
     assert _status(_cfg(shape=(nx, 1000, 1024), faces=walls))[0] == capi.LBM_OK
-    # across a periodic y seam a ragged last tile row takes the plain layout of the same tile
+    # across a periodic y seam a ragged last tile row takes the plain layout of the same tile,
+    # and one thinner than the halo another tile height (1009 = 31 x 32 + 17)
     assert _status(_cfg(shape=(nx, 1000, 1024)))[0] == capi.LBM_OK
+    assert _status(_cfg(shape=(nx, 1009, 1024)))[0] == capi.LBM_OK
     # FP64 (plain layout, 12 x 28 tiles): 86 x 37 tiles, bands of 6 tile rows
     # (256 // 37), 15 rounds, each band's 2 M boundary rows saved
     st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024), storage=capi.LBM_F64))

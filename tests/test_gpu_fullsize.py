@@ -118,6 +118,8 @@ BANDED_CASES = [
     ((5, 282, 999), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),  # ragged, lid on +y
     # even nz, periodic y with a ragged last tile row (8 of 16 rows): the plain layout of the same tile
     ((5, 296, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    # a last row of 16-row tiles thinner than the halo (305 = 19 x 16 + 1): 32 x 32 plain tiles for two steps
+    ((4, 305, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
 ]
 _NAMES = {PERIODIC: "periodic", WALL: "wall", MOVING_WALL: "moving"}
 
@@ -239,7 +241,7 @@ def test_rounds_with_force_match_two_array_bitwise(storage):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("case", [0, 1, 3, 4, 5])
+@pytest.mark.parametrize("case", [0, 1, 3, 4, 5, 6])
 def test_rounds_16bit_in_place_matches_out_of_place(storage, case):
     # 16-bit offset storage in rounds: the saved band boundary rows are raw
     # 16-bit codes.  The merged pass rounds to 16 bits once per two steps (the

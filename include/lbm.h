@@ -76,7 +76,8 @@ typedef enum {
 typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_MOVING_WALL = 2 } lbm_face;
 
 typedef struct {
-    int32_t nx, ny, nz; /* lattice size, x slowest, z fastest; each >= 1 */
+    int32_t nx, ny, nz; /* lattice size, x slowest, z fastest; each >= 1; ny*nz < 2^31 and
+                           ny*nz*(value size) < 4 GiB (LBM_EUNSUPPORTED otherwise) */
     double tau;         /* BGK relaxation time, > 0.5 */
     int32_t storage;    /* lbm_storage */
     int32_t scheme;     /* lbm_scheme */
@@ -88,8 +89,12 @@ typedef struct {
 } lbm_config;
 
 /* Bytes the caller must provide for the distribution buffer (19*N values of
- * the storage type) and for the work buffer of this configuration.  Either
- * output may be NULL.  In-place schemes march y-z tiles with one workgroup
+ * the storage type: the single copy of Sec. 3, which the in-place schemes
+ * update without a second lattice) and for the work buffer of this
+ * configuration (the saved planes that stand in for the bounding-box stages of
+ * Alg. 1 and the slab borders of Sec. 4.2, progress counters, reduction
+ * partials; the two-array baseline's second lattice).  Either output may be
+ * NULL; returns the status lbm_init would return for the configuration.  In-place schemes march y-z tiles with one workgroup
  * each; a plane with more tiles than the device holds workgroups at once runs
  * in rounds over bands of tile rows, whose boundary rows the work buffer then
  * also holds (across a periodic y axis a ragged last tile row then takes the
@@ -108,7 +113,9 @@ lbm_status lbm_init(const lbm_config* cfg, void* f_dev, void* work_dev, const vo
                     const double* rho0_dev, const double* u0_dev, void* hip_stream, lbm_ctx** out);
 
 /* Create a context that adopts the state already in f_dev (resume from a
- * checkpoint: the distribution buffer is the whole state). */
+ * checkpoint: the single copy of the distributions is the whole state of the
+ * method, Sec. 3), without initialising it.  Arguments, ownership and errors
+ * as for lbm_init. */
 lbm_status lbm_attach(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev,
                       void* hip_stream, lbm_ctx** out);
 
@@ -174,7 +181,6 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
 lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches);
 
-/* Rebind the context to another stream (a hipStream_t as void*). */
 /* Test hook for the failure path of the in-place hazard wait: with enable != 0
  * every wait of later in-place passes requires progress no neighbour can
  * reach and gives up after a few polls, as if a neighbouring workgroup had
@@ -183,6 +189,7 @@ lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches);
  * the time-out (LBM_EDEVICE) from then on.  Not for production use. */
 lbm_status lbm_test_force_wait_timeout(lbm_ctx* ctx, int32_t enable);
 
+/* Rebind the context to another stream (a hipStream_t as void*). */
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
 
 /* Message of the last failed call on ctx (or of the last failed lbm_init /

@@ -284,7 +284,8 @@ int32_t orc_macro(const orc_cfg* g, const double* F, const double* f, double* rh
     if (orc_check(g)) return -1;
     tables();
     size_t N = ncell(g);
-    for (size_t i = 0; i < N; ++i) {
+#pragma omp parallel for num_threads(n_threads) schedule(static)
+    for (long long i = 0; i < (long long)N; ++i) {
         double fc[Q], Fc[3], r, uc[3];
         for (int q = 0; q < Q; ++q) fc[q] = f[q * N + i];
         if (F)
@@ -351,7 +352,8 @@ int32_t orc_loss_seed(const orc_cfg* g, const double* F, const double* f, const 
     if (orc_check(g)) return -1;
     tables();
     size_t N = ncell(g);
-    for (size_t i = 0; i < N; ++i) {
+#pragma omp parallel for num_threads(n_threads) schedule(static)
+    for (long long i = 0; i < (long long)N; ++i) {
         double fc[Q], Fc[3], r, uc[3], d[3];
         for (int q = 0; q < Q; ++q) fc[q] = f[q * N + i];
         if (F)
@@ -375,6 +377,7 @@ int32_t orc_stream_adjoint(const orc_cfg* g, const double* lambda_next, double* 
     if (orc_check(g)) return -1;
     tables();
     size_t N = ncell(g);
+#pragma omp parallel for num_threads(n_threads) schedule(static)
     for (int x = 0; x < g->nx; ++x)
         for (int y = 0; y < g->ny; ++y)
             for (int z = 0; z < g->nz; ++z) {
@@ -433,7 +436,8 @@ int32_t orc_adjoint_step(const orc_cfg* g, const double* F, const double* f_t, d
     tables();
     size_t N = ncell(g);
     orc_stream_adjoint(g, lambda, tmp);
-    for (size_t i = 0; i < N; ++i) {
+#pragma omp parallel for num_threads(n_threads) schedule(static)
+    for (long long i = 0; i < (long long)N; ++i) {
         double fc[Q], mu[Q], lam[Q], Fc[3], gF[3] = {0.0, 0.0, 0.0};
         for (int q = 0; q < Q; ++q) {
             fc[q] = f_t[q * N + i];

@@ -43,7 +43,9 @@ class ForceAdjoint(torch.autograd.Function):
             forward_interval(lat, ckpts[-1], dst, n)
             if dst is not None:
                 ckpts.append(dst)
-        _, u, _, _ = lat.macroscopic(want=("u",))
+        # with sums the call waits and reports a hazard wait that gave up in
+        # any in-place pass of the forward (the gradient would be wrong)
+        _, u, _, _ = lat.macroscopic(sums=True, want=("u",))
         ctx.lat, ctx.ckpts, ctx.spec = lat, ckpts, spec
         ctx.save_for_backward(F)
         return u

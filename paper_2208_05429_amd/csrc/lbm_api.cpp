@@ -203,6 +203,9 @@ lbm_status validate(const lbm_config* c, std::string* why)
         return fail(why, LBM_EINVAL, "ny*nz must be below 2^31");
     if (!(c->tau > 0.5) || !isfinite(c->tau)) return fail(why, LBM_EINVAL, "tau must be a finite number > 0.5");
     if (c->storage < LBM_F64 || c->storage > LBM_BF16_OFS) return fail(why, LBM_EINVAL, "unknown storage type");
+    // the kernels address a cell within one direction's y-z plane by a 32-bit byte offset
+    if ((unsigned long long)c->ny * (unsigned long long)c->nz * elem_size(c->storage) >= (1ULL << 32))
+        return fail(why, LBM_EUNSUPPORTED, "one direction's y-z plane must hold less than 4 GiB (ny*nz*value size)");
     if (c->scheme < LBM_TWO_ARRAY || c->scheme > LBM_SWAP2) return fail(why, LBM_EINVAL, "unknown scheme");
     if (c->use_force != 0 && c->use_force != 1) return fail(why, LBM_EINVAL, "use_force must be 0 or 1");
     int moving = 0;

@@ -64,6 +64,14 @@ def test_buffer_sizes():
     assert _status(_cfg(shape=(512, 512, 512)))[0] == capi.LBM_OK
 
 
+def test_planes_of_4_gib_per_direction_are_rejected():
+    # in-plane byte offsets are 32-bit: a direction's y-z plane must stay below 4 GiB
+    assert _status(_cfg(shape=(1, 65536, 16384)))[0] == capi.LBM_EUNSUPPORTED           # FP32, 2^32 bytes
+    assert _status(_cfg(shape=(1, 32768, 16384), storage=capi.LBM_F64))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(shape=(1, 65536, 16384), storage=capi.LBM_BF16_OFS))[0] == capi.LBM_OK  # 2 GiB
+    assert _status(_cfg(shape=(1, 32768, 16384)))[0] == capi.LBM_OK                     # FP32, 2 GiB
+
+
 def test_rounds_plan_for_large_planes():
     # 1024^2 planes need 1024 tiles of 16x64: four rounds of 256 tile rows' bands;
     # the work buffer holds 2 M boundary rows of every band for all x

@@ -274,3 +274,92 @@ def test_merged_adjoint_at_256_cubed_matches_two_single_steps():
     print(f"merged vs single steps at 256^3: lambda {e:.3e}, force gradient {eg:.3e}")
     assert e <= 2e-5 and eg <= 2e-5, (e, eg)
     lat.close()
+
+
+def _oracle_checkpointed_gradient(o, f0, F, ut, steps, k):
+    """(L, dL/dF) of the oracle's discrete adjoint at a size where keeping
+    every state would not fit: states every k steps, each interval's states
+    recomputed by plain steps before its reverse steps.  Only oracle calls, in
+    the order of the plain definition (forward, seed, reverse steps)."""
+    ckpts = [np.array(f0, copy=True)]
+    for _ in range(steps // k):
+        ckpts.append(o.run(ckpts[-1], k, F))
+    L = o.loss(ckpts[-1], ut, F)
+    lam, gF = o.loss_seed(ckpts[-1], ut, F)
+    for seg in range(steps // k - 1, -1, -1):
+        states = [ckpts[seg]]
+        for _ in range(k - 1):
+            states.append(o.run(states[-1], 1, F))
+        for t in range(k - 1, -1, -1):
+            lam, gF = o.adjoint_step(states[t], lam, F, gF)
+    return L, gF
+
+
+def test_adjoint_workload_at_its_stated_size():
+    # 128 x 64 x 64 channel (periodic x, bounce-back walls in y and z), tau 0.8,
+    # rest state, force N(0, 1e-12) per component (seed 1), target u* = u(T)
+    # under a hidden force (seed 2), T = 200, a checkpoint every 20 steps, the
+    # merged reverse pass; finite differences at 16 cells (seed 3) x 3 components
+    import os
+
+    import oracle
+    cfg = wl.CHANNEL_ADJ
+    shape, steps, k, tau = cfg["shape"], cfg["steps"], cfg["checkpoint"], cfg["tau"]
+    oracle.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    o = Oracle(shape, tau, faces=FACES)
+    f0 = o.init()
+    F = wl.normal_field(shape, cfg["force_std"], cfg["force_seed"])
+    hidden = wl.normal_field(shape, cfg["force_std"], cfg["target_seed"])
+    _, ut, _ = o.macro(o.run(f0, steps, hidden), hidden)
+    print("[gpu] oracle checkpointed adjoint 128x64x64 T=200", flush=True)
+    L_ref, g_ref = _oracle_checkpointed_gradient(o, f0, F, ut, steps, k)
+    oracle.set_threads(1)
+    gmax = np.abs(g_ref).max()
+    utt = torch.as_tensor(ut, device="cuda")
+    grads = {}
+    for storage in ("f64", "f32"):
+        print(f"[gpu] merged adjoint {storage} 128x64x64 T=200 checkpoint 20", flush=True)
+        lat0 = Lattice(shape, tau, storage, "swap2", NAMES)  # rest state
+        f0_dev = lat0.f.clone()
+        lat0.close()
+        spec = dict(shape=shape, tau=tau, storage=storage, faces=NAMES, steps=steps, checkpoint=k, merged=True)
+        L, g = force_gradient(torch.as_tensor(F, device="cuda"), f0_dev, spec, utt.to(real_dtype(storage)))
+        grads[storage] = g.double().cpu().numpy()
+        err = np.abs(grads[storage] - g_ref).max() / gmax
+        print(f"{storage}: L {L:.9e} vs oracle {L_ref:.9e}; gradient error vs oracle adjoint {err:.3e}")
+        assert abs(L - L_ref) <= (1e-10 if storage == "f64" else 1e-3) * L_ref
+        assert err <= (1e-10 if storage == "f64" else 1e-3)
+
+    # central differences of the FP64 GPU forward (eps 1e-4 on F, Richardson
+    # with eps/2 to remove the O(eps^2) term of a loss that is not quadratic)
+    f0_64 = Lattice(shape, tau, "f64", "two_array", NAMES).f.clone()
+    Fd = torch.as_tensor(F, device="cuda")
+
+    def loss(Fp):
+        lat = Lattice(shape, tau, "f64", "two_array", NAMES, force=Fp, f=f0_64.clone())
+        lat.step(steps)
+        _, u, _, _ = lat.macroscopic(sums=True, want=("u",))
+        val = float(((u - utt) ** 2).sum())
+        lat.close()
+        return val
+
+    def fd(x, y, z, a, eps):
+        vals = []
+        for sgn in (1, -1):
+            Fp = Fd.clone()
+            Fp[a, x, y, z] += sgn * eps
+            vals.append(loss(Fp))
+        return (vals[0] - vals[1]) / (2 * eps)
+
+    worst = [0.0, 0.0, 0.0]
+    for (x, y, z) in wl.sample_cells(shape, cfg["fd_cells"], cfg["cell_seed"]):
+        for a in range(3):
+            d1, d2 = fd(x, y, z, a, cfg["fd_eps"]), fd(x, y, z, a, cfg["fd_eps"] / 2)
+            rich = (4 * d2 - d1) / 3
+            worst[0] = max(worst[0], abs(rich - grads["f64"][a, x, y, z]) / gmax)
+            worst[1] = max(worst[1], abs(rich - grads["f32"][a, x, y, z]) / gmax)
+            worst[2] = max(worst[2], abs(d1 - grads["f64"][a, x, y, z]) / gmax)
+    print(f"FD (Richardson) vs FP64 adjoint {worst[0]:.3e}, vs FP32 adjoint {worst[1]:.3e}; "
+          f"plain eps=1e-4 FD vs FP64 adjoint {worst[2]:.3e} (of max|grad|)")
+    assert worst[0] <= 1e-6
+    assert worst[1] <= 1e-3

@@ -38,6 +38,7 @@ def gpu_run(shape, tau, storage, scheme, faces=(PERIODIC,) * 6, wall_u=(0, 0, 0)
     lat.step(steps)
     rho, u, un, sums = lat.macroscopic(sums=True)
     torch.cuda.synchronize()
+    lat.unorm = un.cpu().numpy()  # |u| per cell, the quantity Sec. 5.1 compares
     return lat, rho.cpu().numpy(), u.cpu().numpy(), sums
 
 
@@ -54,35 +55,56 @@ def tgv32_ref():
     rho0, u0 = wl.taylor_green_3d(cfg["shape"], cfg["u0"])
     o = Oracle(cfg["shape"], cfg["tau"])
     f = o.run(o.init(rho0, u0), cfg["steps"])
-    rho, u, _ = o.macro(f)
-    return rho0, u0, rho, u, o.sums(f)
+    rho, u, un = o.macro(f)
+    return rho0, u0, rho, u, o.sums(f), un
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_tgv32_fp64_matches_oracle(tgv32_ref, scheme):
     cfg = wl.TGV_32
-    rho0, u0, rho_ref, u_ref, sums_ref = tgv32_ref
-    _, rho, u, sums = gpu_run(cfg["shape"], cfg["tau"], "f64", scheme, rho0=rho0, u0=u0, steps=cfg["steps"])
+    rho0, u0, rho_ref, u_ref, sums_ref, un_ref = tgv32_ref
+    lat, rho, u, sums = gpu_run(cfg["shape"], cfg["tau"], "f64", scheme, rho0=rho0, u0=u0, steps=cfg["steps"])
     assert rel(rho, rho_ref) <= 1e-12
     assert rel(u, u_ref) <= 1e-12
+    assert rel(lat.unorm, un_ref) <= 1e-12
     assert abs(sums[0] - sums_ref[0]) <= 1e-12 * sums_ref[0]
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_tgv32_fp32_matches_oracle(tgv32_ref, scheme):
     cfg = wl.TGV_32
-    rho0, u0, rho_ref, u_ref, _ = tgv32_ref
-    _, rho, u, _ = gpu_run(cfg["shape"], cfg["tau"], "f32", scheme, rho0=rho0, u0=u0, steps=cfg["steps"])
-    eu, er = rel(u, u_ref), rel(rho, rho_ref)
-    print(f"fp32 {scheme}: rho err {er:.3e}  u err {eu:.3e}")
-    assert er <= 2e-6 and eu <= 2e-6
+    rho0, u0, rho_ref, u_ref, _, un_ref = tgv32_ref
+    lat, rho, u, _ = gpu_run(cfg["shape"], cfg["tau"], "f32", scheme, rho0=rho0, u0=u0, steps=cfg["steps"])
+    eu, er, en = rel(u, u_ref), rel(rho, rho_ref), rel(lat.unorm, un_ref)
+    print(f"fp32 {scheme}: rho err {er:.3e}  u err {eu:.3e}  |u| err {en:.3e}")
+    assert er <= 2e-6 and eu <= 2e-6 and en <= 2e-6
+
+
+def test_cavity_fp32_100_steps_matches_oracle():
+    # the lid-driven cavity of the 256^3 workload at 40 x 48 x 56 (several
+    # tiles, ragged last ones): tau 0.52, five static walls, +y lid moving at
+    # 0.05 along x, rest state, 100 steps; every field within 2e-6 of the oracle
+    shape = (40, 48, 56)
+    faces = (WALL, WALL, WALL, MOVING_WALL, WALL, WALL)
+    wall_u = (wl.CAVITY_256["lid_u"], 0.0, 0.0)
+    tau = wl.CAVITY_256["tau"]
+    o = Oracle(shape, tau, faces=faces, wall_u=wall_u)
+    ref = o.run(o.init(), 100)
+    rho_ref, u_ref, un_ref = o.macro(ref)
+    sums_ref = o.sums(ref)
+    for scheme in SCHEMES:
+        lat, rho, u, sums = gpu_run(shape, tau, "f32", scheme, faces, wall_u, steps=100)
+        ef, er, eu, en = rel(lat.distributions(), ref), rel(rho, rho_ref), rel(u, u_ref), rel(lat.unorm, un_ref)
+        print(f"cavity fp32 {scheme}: f {ef:.3e} rho {er:.3e} u {eu:.3e} |u| {en:.3e}")
+        assert max(ef, er, eu, en) <= 2e-6, scheme
+        assert abs(sums[0] - sums_ref[0]) <= 1e-9 * sums_ref[0]
 
 
 @pytest.mark.parametrize("storage,bound", [("f16", 2e-3), ("bf16", 2e-2)])
 def test_tgv32_16bit_storage_error_is_bounded(tgv32_ref, storage, bound):
     # 100 steps of 16-bit rounding of f - w: a loose bound on the accumulated error
     cfg = wl.TGV_32
-    rho0, u0, rho_ref, u_ref, _ = tgv32_ref
+    rho0, u0, rho_ref, u_ref, _, _ = tgv32_ref
     for scheme in ("swap1", "swap2"):
         _, rho, u, _ = gpu_run(cfg["shape"], cfg["tau"], storage, scheme, rho0=rho0, u0=u0, steps=cfg["steps"])
         eu, er = rel(u, u_ref), rel(rho, rho_ref)
@@ -121,10 +143,12 @@ def test_ragged_fp64_full_state(case, steps):
     rho0, u0 = _noisy_init(shape, 100 + case)
     o = Oracle(shape, 0.7, faces=faces, wall_u=wall_u)
     ref = o.run(o.init(rho0, u0), steps)
+    rho_ref, u_ref, un_ref = o.macro(ref)
     for scheme in SCHEMES:
-        lat, _, _, _ = gpu_run(shape, 0.7, "f64", scheme, faces, wall_u, rho0, u0, steps=steps)
+        lat, rho, u, _ = gpu_run(shape, 0.7, "f64", scheme, faces, wall_u, rho0, u0, steps=steps)
         f = lat.distributions()
         assert rel(f, ref) <= 1e-12, scheme
+        assert rel(rho, rho_ref) <= 1e-12 and rel(u, u_ref) <= 1e-12 and rel(lat.unorm, un_ref) <= 1e-12, scheme
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
@@ -134,9 +158,11 @@ def test_ragged_fp32_schemes_agree(case):
     o = Oracle(shape, 0.6, faces=faces, wall_u=wall_u)
     steps = 7
     ref = o.run(o.init(rho0, u0), steps)
-    lat, _, _, _ = gpu_run(shape, 0.6, "f32", "two_array", faces, wall_u, rho0, u0, steps=steps)
+    _, u_ref, un_ref = o.macro(ref)
+    lat, _, u, _ = gpu_run(shape, 0.6, "f32", "two_array", faces, wall_u, rho0, u0, steps=steps)
     a = lat.f.cpu().numpy()
     assert rel(lat.distributions(), ref) <= 2e-6
+    assert rel(u, u_ref) <= 2e-6 and rel(lat.unorm, un_ref) <= 2e-6
     # every in-place kernel shape runs the same per-cell arithmetic as the plain
     # scheme: any difference is a race or an indexing slip
     for variant in VARIANTS:

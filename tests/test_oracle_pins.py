@@ -81,6 +81,62 @@ def test_equilibrium_moments_closed_form():
 
 
 # --------------------------------------------------------------------------
+# the per-cell velocity norm |u|, the quantity Sec. 5.1 compares across
+# algorithms: pinned by states whose norm is known without evaluating it
+# --------------------------------------------------------------------------
+
+# velocities with integer-ratio norms (Pythagorean quadruples a^2+b^2+c^2=d^2)
+PYTHAGOREAN = [((0.02, 0.03, 0.06), 0.07), ((-0.01, 0.04, -0.08), 0.09), ((0.12, -0.03, 0.04), 0.13),
+               ((0.0, -0.06, 0.08), 0.10)]
+
+
+@pytest.mark.parametrize("u0,norm", PYTHAGOREAN)
+def test_velocity_norm_of_uniform_states(u0, norm):
+    # a uniform equilibrium (rho0, u0) has velocity u0 and norm |u0| in every cell
+    shape = (3, 4, 5)
+    o = Oracle(shape, 0.8)
+    rho = np.full(shape, 1.07)
+    u = np.broadcast_to(np.asarray(u0)[:, None, None, None], (3,) + shape).copy()
+    rho_m, u_m, un = o.macro(o.init(rho, u))
+    assert np.abs(un - norm).max() <= 1e-15
+    for a in range(3):
+        assert np.abs(u_m[a] - u0[a]).max() <= 1e-16
+    assert np.abs(rho_m - 1.07).max() <= 2e-15
+
+
+def test_velocity_norm_includes_half_the_force():
+    # u = (j + F/2)/rho: an equilibrium of u0 = (0.01, 0.05, 0.03) at rho = 1.25
+    # under F = (0.025, 0.025, 0) has u = (0.02, 0.06, 0.03), |u| = 0.07
+    shape = (2, 3, 4)
+    o = Oracle(shape, 0.8)
+    u = np.zeros((3,) + shape)
+    u[0], u[1], u[2] = 0.01, 0.05, 0.03
+    F = np.zeros((3,) + shape)
+    F[0], F[1] = 0.025, 0.025
+    _, u_m, un = o.macro(o.init(np.full(shape, 1.25), u), F)
+    assert np.abs(un - 0.07).max() <= 1e-15
+    np.testing.assert_allclose(u_m[:, 0, 0, 0], (0.02, 0.06, 0.03), atol=1e-16)
+
+
+def test_velocity_norm_of_taylor_green_2d_is_its_amplitude_field():
+    # at t = 0 the 2D vortex u = u0 (sin A cos B, -cos A sin B) has the norm
+    # u0 sqrt(sin^2 A cos^2 B + cos^2 A sin^2 B): u0 at (A, B) = (pi/2, 0),
+    # zero at (0, 0), and u0 |sin 2A| / sqrt(2) on the diagonal A = B
+    shape = (16, 16, 3)
+    u0 = 0.04
+    o = Oracle(shape, 0.8)
+    rho, u = wl.taylor_green_2d(shape, u0, axes=(0, 1))
+    _, _, un = o.macro(o.init(rho, u))
+    A = 2 * math.pi * np.arange(16) / 16
+    amp = u0 * np.sqrt(np.sin(A)[:, None] ** 2 * np.cos(A)[None, :] ** 2 +
+                       np.cos(A)[:, None] ** 2 * np.sin(A)[None, :] ** 2)
+    assert np.abs(un - amp[:, :, None]).max() <= 1e-15
+    assert abs(un[4, 0, 1] - u0) <= 1e-16 and un[0, 0, 2] <= 1e-16
+    diag = np.array([un[i, i, 0] for i in range(16)])
+    assert np.abs(diag - u0 * np.abs(np.sin(2 * A)) / math.sqrt(2)).max() <= 1e-15
+
+
+# --------------------------------------------------------------------------
 # exact invariants and fixed points
 # --------------------------------------------------------------------------
 

@@ -29,8 +29,9 @@
  *           it.  The library never allocates device memory: its scratch
  *           (side planes, progress flags, reduction partials, the second
  *           lattice of the two-array scheme) lives in the caller's work
- *           buffer, sized by lbm_buffer_sizes.  Device pointers must be
- *           256-byte aligned.
+ *           buffer, sized by lbm_buffer_sizes (lbm_step_static alone uses a
+ *           fixed static array instead).  Device pointers must be 256-byte
+ *           aligned.
  * Streams   every call is enqueued asynchronously on the context's stream
  *           (a hipStream_t passed as void*; NULL is the legacy default
  *           stream), except lbm_macroscopic with sums_host != NULL, which
@@ -124,6 +125,29 @@ lbm_status lbm_attach(const lbm_config* cfg, void* f_dev, void* work_dev, const 
  * LBM_TWO_ARRAY copies the state back into f_dev after an odd number of steps. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_step
+ * without a context or a work buffer.  Advances the distributions in f_dev
+ * (layout and storage of cfg, as lbm_init writes them) by n >= 0 steps in
+ * place, on hip_stream and the current device, exactly as lbm_step on a
+ * context made from cfg over the same buffers would (same kernels, same
+ * results); force_dev as for lbm_init.  Its scratch (progress counters, saved
+ * planes, band boundary rows; the second lattice of LBM_TWO_ARRAY) is a
+ * static 64 MiB device array that every device the library runs on holds
+ * until the process ends; a configuration whose lbm_buffer_sizes work bytes
+ * exceed it is rejected with LBM_EUNSUPPORTED (512^3 FP32 LBM_SWAP2 needs
+ * 39 MiB).  Every call on a device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race and must not be
+ * made.  The array keeps the last call's contents; each call clears what it
+ * needs clear.  No device or host memory is allocated on the way to the
+ * kernels (a failure's message is kept in host memory).  Asynchronous,
+ * unless timed_out_host is not NULL: it then waits for the passes and
+ * stores 1 if a hazard wait of this call gave up (the state is then not to
+ * be trusted), 0 otherwise.  Errors as for lbm_init, message from
+ * lbm_last_error(NULL). */
+lbm_status lbm_step_static(const lbm_config* cfg, void* f_dev, const void* force_dev, int64_t n, void* hip_stream,
+                           int32_t* timed_out_host);
+
 /* Advance k in {1, 2} steps from the state f_src into f_dst, out of place:
  * f_src is read only and the context's own distribution buffer is neither
  * read nor changed.  Both buffers have the size and layout of f (19N values
@@ -193,7 +217,8 @@ lbm_status lbm_test_force_wait_timeout(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
 
 /* Message of the last failed call on ctx (or of the last failed lbm_init /
- * lbm_attach when ctx is NULL); "" if none.  Valid until the next call. */
+ * lbm_attach / lbm_step_static of this thread when ctx is NULL); "" if
+ * none.  Valid until the next call. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
 /* Release a context; NULL is allowed.  Device buffers stay the caller's. */

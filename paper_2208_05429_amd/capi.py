@@ -51,6 +51,7 @@ def lib():
         L.lbm_init.argtypes = [cfgp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.lbm_attach.argtypes = [cfgp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.lbm_step.argtypes = [_vp, ctypes.c_int64]
+        L.lbm_step_static.argtypes = [cfgp, _vp, _vp, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int32)]
         L.lbm_step_into.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.lbm_macroscopic.argtypes = [_vp, _vp, _vp, _vp, dp]
         L.lbm_macro_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -63,8 +64,8 @@ def lib():
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_destroy.argtypes = [_vp]
         L.lbm_destroy.restype = None
-        for name in ("lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_step_into", "lbm_macroscopic",
-                     "lbm_macro_adjoint", "lbm_step_adjoint", "lbm_set_stream", "lbm_set_kernel_timing",
+        for name in ("lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_step_static", "lbm_step_into",
+                     "lbm_macroscopic", "lbm_macro_adjoint", "lbm_step_adjoint", "lbm_set_stream", "lbm_set_kernel_timing",
                      "lbm_kernel_time", "lbm_test_force_wait_timeout"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -120,6 +121,16 @@ def lbm_attach(cfg, f_dev, work_dev, force_dev, stream):
 
 def lbm_step(ctx, n):
     _check(lib().lbm_step(ctx, int(n)), ctx)
+
+
+def lbm_step_static(cfg, f_dev, force_dev, n, stream, report_timeout=False):
+    """Returns True if a hazard wait of the call gave up (only with
+    report_timeout, which makes the call wait for its passes)."""
+    t = ctypes.c_int32(0)
+    st = lib().lbm_step_static(ctypes.byref(cfg), f_dev, force_dev, int(n), stream,
+                               ctypes.byref(t) if report_timeout else None)
+    _check(st, None)
+    return bool(t.value)
 
 
 def lbm_step_into(ctx, f_src_dev, f_dst_dev, k):

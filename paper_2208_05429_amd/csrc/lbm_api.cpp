@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,14 @@
 #include "march_dispatch.hpp"
 
 using namespace lbm;
+
+// Scratch of lbm_step_static, the entry point for callers that cannot
+// allocate device memory: one copy on every device the library runs on,
+// loaded with the library and held until the process ends.  Host code uses
+// the per-device address from hipGetSymbolAddress (static_scratch below),
+// never the array's name, which is only a host-side stand-in.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 struct lbm_ctx {
     lbm_config cfg;
@@ -142,21 +151,23 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     r.nty_band = r.nty;
     if (tiles > cap) {
         // rounds over bands of tile rows, each band's boundary rows saved first
-        const std::string need = "the y-z plane needs " + std::to_string(tiles) +
-                                 " marching workgroups, more than can be co-resident (" + std::to_string(cap) + ")";
-        if (r.ntz > cap) return fail(why, LBM_EUNSUPPORTED, need + ", even for one row of tiles");
+        auto need = [&]() {
+            return "the y-z plane needs " + std::to_string(tiles) +
+                   " marching workgroups, more than can be co-resident (" + std::to_string(cap) + ")";
+        };
+        if (r.ntz > cap) return fail(why, LBM_EUNSUPPORTED, need() + ", even for one row of tiles");
         // Across the periodic y seam the last row of tiles reads the first
         // band's saved rows.  The pair-and-ring layout reads them only in the
         // ring rows above a whole tile; the plain layout in any frame row, but
         // only the last row of tiles may reach across the seam.
         if (py && c.ny % r.TY != 0 && (r.pr || c.ny % r.TY < M))
             return fail(why, LBM_EUNSUPPORTED,
-                        need + (r.pr ? "; rounds on a periodic y axis need whole tile rows"
+                        need() + (r.pr ? "; rounds on a periodic y axis need whole tile rows"
                                      : "; rounds on a periodic y axis need a last row of tiles at least as thick as the halo"));
         r.nty_band = cap / r.ntz;
         r.nbands = (r.nty + r.nty_band - 1) / r.nty_band;
         if (c.ny - (r.nbands - 1) * r.nty_band * r.TY < M)
-            return fail(why, LBM_EUNSUPPORTED, need + "; the last band of rows is thinner than the halo");
+            return fail(why, LBM_EUNSUPPORTED, need() + "; the last band of rows is thinner than the halo");
     }
     const int tiles_run = r.nty_band * r.ntz;  // work items of one round, per segment
     // a periodic axis whose last tile is thinner than M lets halos reach two tiles away
@@ -281,22 +292,19 @@ int device_cap(const lbm_config& c, const MarchPlan& p)
     }
 }
 
-lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev, void* stream,
-                  lbm_ctx** out)
+// Fills a context for cfg over the given buffers: geometry, pass plans for
+// the device's co-residency and the work-buffer offsets.  work_cap: bytes
+// available at work_dev (checked against the layout), or 0 when the caller
+// sized the buffer with lbm_buffer_sizes.
+lbm_status setup(lbm_ctx* ctx, const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev, void* stream,
+                 size_t work_cap, std::string* why)
 {
-    if (out) *out = nullptr;
-    g_create_err.clear();
-    if (!out) return fail(&g_create_err, LBM_EINVAL, "out is NULL");
-    lbm_status st = validate(cfg, &g_create_err);
+    lbm_status st = validate(cfg, why);
     if (st != LBM_OK) return st;
-    if (!f_dev || !work_dev) return fail(&g_create_err, LBM_EINVAL, "f_dev and work_dev are required");
-    if (!aligned(f_dev) || !aligned(work_dev))
-        return fail(&g_create_err, LBM_EINVAL, "device buffers must be 256-byte aligned");
-    if (cfg->use_force && !force_dev) return fail(&g_create_err, LBM_EINVAL, "use_force needs force_dev");
-    if (force_dev && !aligned(force_dev)) return fail(&g_create_err, LBM_EINVAL, "force_dev must be 256-byte aligned");
-
-    lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
-    if (!ctx) return fail(&g_create_err, LBM_EDEVICE, "out of host memory");
+    if (!f_dev || !work_dev) return fail(why, LBM_EINVAL, "f_dev and work_dev are required");
+    if (!aligned(f_dev) || !aligned(work_dev)) return fail(why, LBM_EINVAL, "device buffers must be 256-byte aligned");
+    if (cfg->use_force && !force_dev) return fail(why, LBM_EINVAL, "use_force needs force_dev");
+    if (force_dev && !aligned(force_dev)) return fail(why, LBM_EINVAL, "force_dev must be 256-byte aligned");
     ctx->cfg = *cfg;
     ctx->f = f_dev;
     ctx->work = static_cast<unsigned char*>(work_dev);
@@ -320,39 +328,52 @@ lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void
     size_t off[6], total = 0, sized = 0;
     int cap = kMaxResident;
     MarchPlan probe[3];
-    st = layout(*cfg, cap, probe, off, &sized, &g_create_err);  // what lbm_buffer_sizes reported
-    if (st != LBM_OK) {
-        delete ctx;
-        return st;
+    st = layout(*cfg, cap, probe, off, &sized, why);  // what lbm_buffer_sizes reported
+    if (st != LBM_OK) return st;
+    if (work_cap && sized > work_cap) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "this configuration needs %zu bytes of scratch, more than the %zu available", sized,
+                 work_cap);
+        return fail(why, LBM_EUNSUPPORTED, msg);
     }
     if (cfg->scheme != LBM_TWO_ARRAY) {
         // the device may hold fewer marching workgroups than the sizing bound
         for (int M = 1; M <= 2; ++M) {
             if (probe[M].M == 0) continue;
             const int dc = device_cap(*cfg, probe[M]);
-            if (dc <= 0) {
-                delete ctx;
-                return fail(&g_create_err, LBM_EDEVICE, "cannot query the co-residency of the marching kernel");
-            }
+            if (dc <= 0) return fail(why, LBM_EDEVICE, "cannot query the co-residency of the marching kernel");
             if (dc < cap) cap = dc;
         }
     }
-    st = layout(*cfg, cap, ctx->plan, off, &total, &g_create_err);
-    if (st != LBM_OK) {
-        delete ctx;
-        return st;
-    }
-    if (total > sized) {
-        delete ctx;
-        return fail(&g_create_err, LBM_EUNSUPPORTED,
+    st = layout(*cfg, cap, ctx->plan, off, &total, why);
+    if (st != LBM_OK) return st;
+    if (total > sized)
+        return fail(why, LBM_EUNSUPPORTED,
                     "this device holds fewer co-resident marching workgroups than the work-buffer size assumed");
-    }
     ctx->off_partials = off[0];
     ctx->off_sums = off[1];
     ctx->off_second = off[2];
     ctx->off_flags = off[3];
     ctx->off_side = off[4];
     ctx->off_shell = off[5];
+    return LBM_OK;
+}
+
+lbm_status create(const lbm_config* cfg, void* f_dev, void* work_dev, const void* force_dev, void* stream,
+                  lbm_ctx** out)
+{
+    if (out) *out = nullptr;
+    g_create_err.clear();
+    if (!out) return fail(&g_create_err, LBM_EINVAL, "out is NULL");
+    lbm_status st = validate(cfg, &g_create_err);
+    if (st != LBM_OK) return st;
+    lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+    if (!ctx) return fail(&g_create_err, LBM_EDEVICE, "out of host memory");
+    st = setup(ctx, cfg, f_dev, work_dev, force_dev, stream, 0, &g_create_err);
+    if (st != LBM_OK) {
+        delete ctx;
+        return st;
+    }
     if (cfg->scheme != LBM_TWO_ARRAY) {
         // the timeout report of the in-place passes starts clear (the work
         // buffer arrives uninitialised) and is never cleared by a pass
@@ -464,6 +485,62 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
     return device_err(ctx, e, "marching kernel launch");
 }
 
+// Device address of this device's copy of the static scratch, looked up once
+// per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];
+
+lbm_status static_scratch(void** out, std::string* why)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(why, LBM_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(why, LBM_EUNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(why, LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return LBM_OK;
+}
+
+// n > 0 steps on a prepared context (the body of lbm_step)
+lbm_status step_n(lbm_ctx* ctx, int64_t n)
+{
+    lbm_status st = LBM_OK;
+    switch (ctx->cfg.scheme) {
+    case LBM_TWO_ARRAY: {
+        void* second = ctx->work + ctx->off_second;
+        for (int64_t k = 0; k < n && st == LBM_OK; ++k) {
+            const void* src = (k & 1) ? second : ctx->f;
+            void* dst = (k & 1) ? ctx->f : second;
+            const long tix = timing_begin(ctx, 1);
+            st = device_err(ctx,
+                            launch_two_array(ctx->cfg.storage, ctx->force != nullptr, ctx->g, src, dst, ctx->force,
+                                             ctx->stream),
+                            "two-array step launch");
+            timing_end(ctx, tix);
+        }
+        if (st == LBM_OK && (n & 1))
+            st = device_err(ctx, launch_copy(ctx->cfg.storage, ctx->g, second, ctx->f, ctx->stream), "state copy");
+        break;
+    }
+    case LBM_SWAP1:
+        for (int64_t k = 0; k < n && st == LBM_OK; ++k) st = march_pass(ctx, 1, ctx->f, ctx->f);
+        break;
+    default:
+        for (int64_t k = 0; k < n / 2 && st == LBM_OK; ++k) st = march_pass(ctx, 2, ctx->f, ctx->f);
+        if (st == LBM_OK && (n & 1)) st = march_pass(ctx, 1, ctx->f, ctx->f);
+        break;
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -514,32 +591,42 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n)
     ctx->err.clear();
     if (n < 0) return fail(&ctx->err, LBM_EINVAL, "n must be >= 0");
     if (n == 0) return LBM_OK;
-    lbm_status st = LBM_OK;
-    switch (ctx->cfg.scheme) {
-    case LBM_TWO_ARRAY: {
-        void* second = ctx->work + ctx->off_second;
-        for (int64_t k = 0; k < n && st == LBM_OK; ++k) {
-            const void* src = (k & 1) ? second : ctx->f;
-            void* dst = (k & 1) ? ctx->f : second;
-            const long tix = timing_begin(ctx, 1);
-            st = device_err(ctx,
-                            launch_two_array(ctx->cfg.storage, ctx->force != nullptr, ctx->g, src, dst, ctx->force,
-                                             ctx->stream),
-                            "two-array step launch");
-            timing_end(ctx, tix);
+    return step_n(ctx, n);
+}
+
+lbm_status lbm_step_static(const lbm_config* cfg, void* f_dev, const void* force_dev, int64_t n, void* hip_stream,
+                           int32_t* timed_out_host)
+{
+    g_create_err.clear();
+    if (timed_out_host) *timed_out_host = 0;
+    lbm_status st = validate(cfg, &g_create_err);
+    if (st != LBM_OK) return st;
+    if (n < 0) return fail(&g_create_err, LBM_EINVAL, "n must be >= 0");
+    void* work = nullptr;
+    st = static_scratch(&work, &g_create_err);
+    if (st != LBM_OK) return st;
+    lbm_ctx ctx;  // on the stack: no allocation on the way to the kernels
+    st = setup(&ctx, cfg, f_dev, work, force_dev, hip_stream, kStaticScratchBytes, &g_create_err);
+    if (st != LBM_OK) return st;
+    if (n == 0) return LBM_OK;
+    int* word = reinterpret_cast<int*>(ctx.work + ctx.off_flags);
+    if (cfg->scheme != LBM_TWO_ARRAY) {
+        // the scratch keeps the previous call's contents: the time-out report
+        // starts clear for this call (progress counters and saved planes are
+        // rewritten by every pass before they are read)
+        st = device_err(&ctx, launch_clear_word(word, ctx.stream), "timeout word clear");
+        if (st == LBM_OK) st = step_n(&ctx, n);
+        if (st == LBM_OK && timed_out_host) {
+            int t = 0;
+            st = device_err(&ctx, hipMemcpyAsync(&t, word, sizeof(int), hipMemcpyDeviceToHost, ctx.stream),
+                            "progress-word copy");
+            if (st == LBM_OK) st = device_err(&ctx, hipStreamSynchronize(ctx.stream), "stream synchronize");
+            if (st == LBM_OK) *timed_out_host = t != 0;
         }
-        if (st == LBM_OK && (n & 1))
-            st = device_err(ctx, launch_copy(ctx->cfg.storage, ctx->g, second, ctx->f, ctx->stream), "state copy");
-        break;
+    } else {
+        st = step_n(&ctx, n);
     }
-    case LBM_SWAP1:
-        for (int64_t k = 0; k < n && st == LBM_OK; ++k) st = march_pass(ctx, 1, ctx->f, ctx->f);
-        break;
-    default:
-        for (int64_t k = 0; k < n / 2 && st == LBM_OK; ++k) st = march_pass(ctx, 2, ctx->f, ctx->f);
-        if (st == LBM_OK && (n & 1)) st = march_pass(ctx, 1, ctx->f, ctx->f);
-        break;
-    }
+    if (st != LBM_OK) g_create_err = ctx.err;
     return st;
 }
 

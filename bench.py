@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="target length of the oracle sample (the estimate from a short timing runs long, so the sample lands near 10-20 s)")
     ap.add_argument("--copy-probe", type=int, default=1 << 31, metavar="BYTES",
-                    help="device-to-device copy of BYTES bytes: achievable read+write rate, counter calibration")
+                    help="device-to-device copy of BYTES bytes (a multiple of 16; 0 skips the probes): achievable "
+                         "read+write rate, counter calibration; also runs the access-pattern probe on the lattice")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-storage-sweep", action="store_true", help="skip the FP16/BF16 storage runs")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 single-copy run")
@@ -277,6 +278,7 @@ def main():
         print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
     import torch
+    from paper_2208_05429_amd import capi
     from paper_2208_05429_amd import workloads as wl
     from paper_2208_05429_amd.lattice import Lattice
 
@@ -388,27 +390,60 @@ def main():
         out["roofline"]["single_step_launch"] = {
             "launches": kn[0], "avg_kernel_ms": round(ms1, 4),
             "achieved": round(2 * 19 * s * N / (ms1 * 1e-3) / 1e9, 1)}
+    if a.copy_probe and a.scheme != "two_array" and a.storage != "f64" and shape[2] % 2 == 0:
+        # the kernel's access pattern without its compute (the library's
+        # pattern probe: same work items and pair accesses, no halo, no LDS,
+        # no hazard checks; it stores back what it loaded)
+        try:
+            t = []
+            for _ in range(4):
+                c0, c1 = _events()
+                c0.record(stream)
+                capi.lbm_probe_pattern(lat.cfg, lat.f.data_ptr(), M, stream.cuda_stream)
+                c1.record(stream)
+                torch.cuda.synchronize()
+                t.append(c0.elapsed_time(c1))
+            pms = float(np.median(t[1:]))
+            pgbs = alg_bytes / (pms * 1e-3) / 1e9
+            out["pattern_probe"] = {"ms_per_pass": round(pms, 4), "gbs": round(pgbs, 1),
+                                    "frac_of_peak": round(pgbs / HBM_PEAK_GBS, 4),
+                                    "kernel_frac_of_pattern": round(achieved / pgbs, 4)}
+        except capi.LbmError as ex:
+            out["pattern_probe"] = {"unsupported": str(ex)}
     lat.close()
     del lat
     torch.cuda.empty_cache()
     if a.copy_probe:
-        # the achievable rate of a plain device copy (same 1:1 read/write mix)
+        # achievable rate of the 1:1 read/write mix of an in-place pass: the
+        # library's 16-byte streaming copy (on the marching kernel's grid of
+        # 256 workgroups, and on larger grids), and torch's device copy
         src = torch.empty(a.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        best = 1e30
-        for _ in range(3):
-            c0, c1 = _events()
-            c0.record(stream)
-            dst.copy_(src)
-            c1.record(stream)
+
+        def best_of(fn, reps=4):
+            fn()
             torch.cuda.synchronize()
-            best = min(best, c0.elapsed_time(c1))
-        copy_gbs = 2 * a.copy_probe / (best * 1e-3) / 1e9
-        out["roofline"]["copy_gbs"] = round(copy_gbs, 1)
+            best = 1e30
+            for _ in range(reps):
+                c0, c1 = _events()
+                c0.record(stream)
+                fn()
+                c1.record(stream)
+                torch.cuda.synchronize()
+                best = min(best, c0.elapsed_time(c1))
+            return 2 * a.copy_probe / (best * 1e-3) / 1e9
+
+        hip = {b: round(best_of(lambda: capi.lbm_probe_copy(src.data_ptr(), dst.data_ptr(), a.copy_probe, b,
+                                                             stream.cuda_stream)), 1)
+               for b in (256, 1024, 4096)}
+        torch_gbs = best_of(lambda: dst.copy_(src))
+        copy_gbs = max(hip.values())
+        out["roofline"]["copy_gbs"] = copy_gbs
         out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
-        out["copy_probe"] = {"bytes": a.copy_probe, "ms": round(best, 4)}
+        out["copy_probe"] = {"bytes": a.copy_probe, "hip_copy16_gbs_by_grid": hip,
+                             "torch_copy_gbs": round(torch_gbs, 1)}
+        if "pattern_probe" in out and "gbs" in out["pattern_probe"]:
+            out["pattern_probe"]["frac_of_copy"] = round(out["pattern_probe"]["gbs"] / copy_gbs, 4)
         del src, dst
         torch.cuda.empty_cache()
     headline = a.storage == "f32" and a.scheme == "swap2" and a.workload == "tgv" and a.shape is None

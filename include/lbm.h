@@ -205,6 +205,26 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
 lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches);
 
+/* Measurement probes: they compute nothing of the method and bound what the
+ * marching kernel can reach on the device's memory (the roofline argument of
+ * the measurement).  Asynchronous on hip_stream; errors as for lbm_init, with
+ * the message from lbm_last_error(NULL).
+ *
+ * lbm_probe_copy: copy `bytes` (a multiple of 16) from src_dev to dst_dev
+ * (non-overlapping, 256-byte aligned) with 16-byte loads and stores per lane,
+ * one launch of `blocks` workgroups of 512 threads (256: the marching
+ * kernel's grid on this device).
+ *
+ * lbm_probe_pattern: the access pattern of one marching pass of
+ * steps_per_pass (1 or 2) steps of cfg over f_dev (19N values of the 32- or
+ * 16-bit storage, even nz, one round of 16 x 64 tiles: LBM_EUNSUPPORTED
+ * otherwise): the same work items and pair layout, 19 pair loads of each
+ * plane and 19 pair stores, in place, steps_per_pass planes behind, without
+ * halo, LDS exchange, compute or hazard checks.  It stores back what it
+ * loaded, so f_dev is unchanged. */
+lbm_status lbm_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, int32_t blocks, void* hip_stream);
+lbm_status lbm_probe_pattern(const lbm_config* cfg, void* f_dev, int32_t steps_per_pass, void* hip_stream);
+
 /* Test hook for the failure path of the in-place hazard wait: with enable != 0
  * every wait of later in-place passes requires progress no neighbour can
  * reach and gives up after a few polls, as if a neighbouring workgroup had
@@ -216,9 +236,9 @@ lbm_status lbm_test_force_wait_timeout(lbm_ctx* ctx, int32_t enable);
 /* Rebind the context to another stream (a hipStream_t as void*). */
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
 
-/* Message of the last failed call on ctx (or of the last failed lbm_init /
- * lbm_attach / lbm_step_static of this thread when ctx is NULL); "" if
- * none.  Valid until the next call. */
+/* Message of the last failed call on ctx (or, when ctx is NULL, of this
+ * thread's last failed call that takes no context: lbm_init, lbm_attach,
+ * lbm_step_static, the probes); "" if none.  Valid until the next call. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
 /* Release a context; NULL is allowed.  Device buffers stay the caller's. */

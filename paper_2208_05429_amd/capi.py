@@ -53,6 +53,8 @@ def lib():
         L.lbm_step.argtypes = [_vp, ctypes.c_int64]
         L.lbm_step_static.argtypes = [cfgp, _vp, _vp, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_int32)]
         L.lbm_step_into.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
+        L.lbm_probe_copy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int32, _vp]
+        L.lbm_probe_pattern.argtypes = [cfgp, _vp, ctypes.c_int32, _vp]
         L.lbm_macroscopic.argtypes = [_vp, _vp, _vp, _vp, dp]
         L.lbm_macro_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.lbm_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32]
@@ -66,7 +68,7 @@ def lib():
         L.lbm_destroy.restype = None
         for name in ("lbm_buffer_sizes", "lbm_init", "lbm_attach", "lbm_step", "lbm_step_static", "lbm_step_into",
                      "lbm_macroscopic", "lbm_macro_adjoint", "lbm_step_adjoint", "lbm_set_stream", "lbm_set_kernel_timing",
-                     "lbm_kernel_time", "lbm_test_force_wait_timeout"):
+                     "lbm_kernel_time", "lbm_test_force_wait_timeout", "lbm_probe_copy", "lbm_probe_pattern"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -161,6 +163,14 @@ def lbm_set_kernel_timing(ctx, enable):
 
 def lbm_test_force_wait_timeout(ctx, enable):
     _check(lib().lbm_test_force_wait_timeout(ctx, 1 if enable else 0), ctx)
+
+
+def lbm_probe_copy(src_dev, dst_dev, nbytes, blocks, stream):
+    _check(lib().lbm_probe_copy(src_dev, dst_dev, int(nbytes), int(blocks), stream), None)
+
+
+def lbm_probe_pattern(cfg, f_dev, steps_per_pass, stream):
+    _check(lib().lbm_probe_pattern(ctypes.byref(cfg), f_dev, int(steps_per_pass), stream), None)
 
 
 def lbm_kernel_time(ctx):

@@ -735,6 +735,51 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
                       "adjoint step launch");
 }
 
+lbm_status lbm_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, int32_t blocks, void* hip_stream)
+{
+    g_create_err.clear();
+    if (!src_dev || !dst_dev) return fail(&g_create_err, LBM_EINVAL, "src_dev and dst_dev are required");
+    if (!aligned(src_dev) || !aligned(dst_dev))
+        return fail(&g_create_err, LBM_EINVAL, "device buffers must be 256-byte aligned");
+    if (bytes % 16 != 0) return fail(&g_create_err, LBM_EINVAL, "bytes must be a multiple of 16");
+    if (blocks < 1 || blocks > (1 << 20)) return fail(&g_create_err, LBM_EINVAL, "blocks must be in [1, 2^20]");
+    const char* a0 = static_cast<const char*>(src_dev);
+    const char* b0 = static_cast<const char*>(dst_dev);
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(&g_create_err, LBM_EINVAL, "src and dst overlap");
+    const hipError_t e = launch_probe_copy(src_dev, dst_dev, (long long)(bytes / 16), blocks,
+                                           static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(&g_create_err, LBM_EDEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_probe_pattern(const lbm_config* cfg, void* f_dev, int32_t steps_per_pass, void* hip_stream)
+{
+    g_create_err.clear();
+    lbm_status st = validate(cfg, &g_create_err);
+    if (st != LBM_OK) return st;
+    if (!f_dev || !aligned(f_dev)) return fail(&g_create_err, LBM_EINVAL, "f_dev must be a 256-byte aligned buffer");
+    if (steps_per_pass != 1 && steps_per_pass != 2)
+        return fail(&g_create_err, LBM_EINVAL, "steps_per_pass must be 1 or 2");
+    if (cfg->storage == LBM_F64 || cfg->nz % 2 != 0 || cfg->variant != 0)
+        return fail(&g_create_err, LBM_EUNSUPPORTED,
+                    "the pattern probe replicates the pair layout: 32- or 16-bit storage, even nz, variant 0");
+    MarchPlan p;
+    st = make_plan(*cfg, steps_per_pass, kMaxResident, &p, &g_create_err);
+    if (st != LBM_OK) return st;
+    if (!p.pr || p.TY != 16 || p.TZ != 64 || p.nbands != 1)
+        return fail(&g_create_err, LBM_EUNSUPPORTED, "the pattern probe is built for one round of 16x64 tiles");
+    Geom g{};
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nz = cfg->nz;
+    g.N = (long long)cfg->nx * cfg->ny * cfg->nz;
+    g.PL = (long long)cfg->ny * cfg->nz;
+    const hipError_t e = launch_probe_pattern(cfg->storage, g, p, f_dev, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess)
+        return fail(&g_create_err, LBM_EDEVICE, std::string("pattern probe: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
 lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable)
 {
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;

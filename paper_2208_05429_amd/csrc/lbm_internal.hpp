@@ -93,6 +93,9 @@ hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const vo
                                 const void* grad_u, void* lambda, void* grad_force, hipStream_t s);
 hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, const void* f_t, const void* F,
                                const void* lam_in, void* lam_out, void* grad_force, hipStream_t s);
+// measurement probes (k_probe.hip)
+hipError_t launch_probe_copy(const void* src, void* dst, long long n16, int blocks, hipStream_t s);
+hipError_t launch_probe_pattern(int storage, const Geom& g, const MarchPlan& p, void* f, hipStream_t s);
 hipError_t launch_step_adjoint2(int storage, const Geom& g, const void* f_t, const void* F, const void* lam_in,
                                 void* lam_out, void* grad_force, hipStream_t s);
 

@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-storage-sweep", action="store_true", help="skip the FP16/BF16 storage runs")
     ap.add_argument("--no-large", action="store_true", help="skip the 1024^3 single-copy run")
+    ap.add_argument("--no-cpu-context", action="store_true",
+                    help="skip the paper's sequential CPU algorithms (Fuse Swap, two-step, prism) on the host")
     return ap.parse_args()
 
 
@@ -113,6 +115,31 @@ def cpu_baseline(target_s):
             "sample": f"64^3 periodic Taylor-Green+noise, tau=0.6, {steps} steps, FP64 two-array, {el:.1f} s",
             "value_1_thread": round(n * steps1 / el1 / 1e6, 3), "sample_1_thread": f"{steps1} steps, {el1:.1f} s",
             "cpu": _cpu_model()}
+
+
+def cpu_context(size=256, steps=2):
+    """The paper's own sequential CPU algorithms (liblbm_cpu.so, one thread,
+    FP64, the lid-driven cavity of Sec. 5.1 at size^3): Fuse Swap (Alg. 1),
+    the two-step sweep (Alg. 2) in lexicographic order and with the prism
+    traversal.  Context for the paper's relative CPU speedups (Sec. 5.2), not a
+    target: MLUPS of each and the two-step variants' ratio to Fuse Swap."""
+    from paper_2208_05429_amd import capi, host
+    shape = (size,) * 3
+    cfg = capi.make_config(shape, 0.52, faces=(1, 1, 1, 2, 1, 1), wall_u=(0.05, 0.0, 0.0))
+    g = host.lbm_cpu_init(cfg)
+    host.lbm_cpu_fuse_swap(cfg, g, 1)  # first touch
+    runs = {"fuse_swap": lambda: host.lbm_cpu_fuse_swap(cfg, g, steps),
+            "two_step": lambda: host.lbm_cpu_two_step(cfg, g, steps, 0),
+            "two_step_prism16": lambda: host.lbm_cpu_two_step(cfg, g, steps, 16),
+            "two_step_prism64": lambda: host.lbm_cpu_two_step(cfg, g, steps, 64)}
+    out = {}
+    for name, fn in runs.items():
+        t0 = time.perf_counter()
+        fn()
+        out[name] = round(size ** 3 * steps / (time.perf_counter() - t0) / 1e6, 2)
+    return {"MLUPS": out, "vs_fuse_swap": {k: round(v / out["fuse_swap"], 3) for k, v in out.items() if k != "fuse_swap"},
+            "workload": f"{size}^3 lid-driven cavity, tau 0.52, FP64, {steps} steps each, one thread",
+            "paper_two_step_prism_vs_fuse_prism_sequential": {"Haswell": 1.188, "Skylake": 1.155, "KNL": 1.0115}}
 
 
 def _cpu_model():
@@ -467,6 +494,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     else:
         out["cpu_baseline"] = None
+    if not a.no_cpu_context:
+        print("[bench] the paper's CPU algorithms on the host", file=sys.stderr, flush=True)
+        out["cpu_context"] = cpu_context()
     print(json.dumps(out), flush=True)
 
 

@@ -1,10 +1,13 @@
-"""Builds liblbm.so (the HIP library behind include/lbm.h) in-tree for gfx950.
+"""Builds liblbm.so (the HIP library behind include/lbm.h) in-tree for gfx950,
+and liblbm_cpu.so (the paper's sequential CPU algorithms behind
+include/lbm_cpu.h, host context).
 
     python -m paper_2208_05429_amd.build [--resource-usage]
 
 Every source under csrc/ is compiled by hipcc to an object in _build/ (in
 parallel) and linked into paper_2208_05429_amd/liblbm.so.  Packed FP32 vector
-instructions are disabled for all device code.
+instructions are disabled for all device code.  host/lbm_cpu.cpp is compiled by
+g++ (-O3, no fast-math) into paper_2208_05429_amd/liblbm_cpu.so.
 """
 from __future__ import annotations
 
@@ -18,6 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build", "lbm")
 LIB = os.path.join(HERE, "liblbm.so")
+CPU_SRC = os.path.join(HERE, "host", "lbm_cpu.cpp")
+CPU_LIB = os.path.join(HERE, "liblbm_cpu.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -57,7 +62,20 @@ def _compile(src, resource_usage):
     return src, obj, p.returncode, p.stdout + p.stderr
 
 
+def build_cpu() -> str:
+    """The host library of the paper's CPU algorithms (g++, one thread)."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = [os.environ.get("CXX", "g++"), "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+           f"-I{os.path.join(os.path.dirname(HERE), 'include')}", "-o", tmp, CPU_SRC]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"g++ failed on lbm_cpu.cpp:\n{p.stdout}{p.stderr}")
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(resource_usage: bool = False, jobs: int | None = None, verbose: bool = False) -> str:
+    build_cpu()
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))

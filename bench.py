@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--scheme", default="swap2", choices=["swap2", "swap1", "two_array"])
+    ap.add_argument("--scheme", default="swap2", choices=["swap2", "swap1", "two_array", "swap3"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16", "bf16"])
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--workload", default="tgv", choices=["tgv", "cavity", "large", "channel"],
@@ -370,16 +370,19 @@ def main():
         sys.exit(3)
 
     mlups = N * a.steps / (ms * 1e-3) / 1e6
-    # The merged scheme runs steps // 2 two-step launches and, for an odd
-    # count, one single-step launch; the roofline is that of the two-step
-    # launches (the dominant kernel), the single-step one is reported beside.
-    M = 2 if (a.scheme == "swap2" and kn[1] > 0) else 1
-    k = 1 if M == 2 else 0
+    # A merged scheme runs steps // M launches of M steps and, for a remainder,
+    # one shorter launch; the roofline is that of the M-step launches (the
+    # dominant kernel), the remainder's launch is reported beside.
+    Mmax = {"swap2": 2, "swap3": 3}.get(a.scheme, 1)
+    M = next((m for m in range(Mmax, 0, -1) if kn[m - 1] > 0), 1)
+    k = M - 1
     avg_kernel_ms = kms[k] / max(kn[k], 1)
     s = BYTES[a.storage]
     alg_bytes = 2 * 19 * s * N  # one read and one write of the single copy per launch
     achieved = alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
     kernel_key = (f"march_M{M}_{a.storage}_{a.size}" if a.scheme != "two_array" else f"two_array_{a.storage}_{a.size}")
+    if a.variant:
+        kernel_key += f"_v{a.variant}"
     if a.shape is not None:
         kernel_key += "_" + sname
     if a.workload != "tgv":
@@ -411,12 +414,13 @@ def main():
     if traffic:
         # measured HBM bytes (rocprofv3, calibrated) over the same launch time
         out["roofline"]["measured_gbs"] = round(traffic / (avg_kernel_ms * 1e-3) / 1e9, 1)
-    if a.scheme == "swap2" and kn[0] > 0 and kn[1] > 0:
-        # the single-step launch of an odd step count
-        ms1 = kms[0] / kn[0]
-        out["roofline"]["single_step_launch"] = {
-            "launches": kn[0], "avg_kernel_ms": round(ms1, 4),
-            "achieved": round(2 * 19 * s * N / (ms1 * 1e-3) / 1e9, 1)}
+    for m in range(1, M):
+        if kn[m - 1] > 0:
+            # the launch of the remaining steps (fewer than M)
+            msr = kms[m - 1] / kn[m - 1]
+            out["roofline"][f"remainder_launch_{m}_steps"] = {
+                "launches": kn[m - 1], "avg_kernel_ms": round(msr, 4),
+                "achieved": round(2 * 19 * s * N / (msr * 1e-3) / 1e9, 1)}
     if a.copy_probe and a.scheme != "two_array" and a.storage != "f64" and shape[2] % 2 == 0:
         # the kernel's access pattern without its compute (the library's
         # pattern probe: same work items and pair accesses, no halo, no LDS,

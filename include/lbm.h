@@ -71,7 +71,9 @@ typedef enum {
 typedef enum {
     LBM_TWO_ARRAY = 0, /* plain baseline: collide + push-stream into a second lattice (work buffer) */
     LBM_SWAP1 = 1,     /* in place, single copy, one step per pass (Sec. 3, Alg. 1) */
-    LBM_SWAP2 = 2      /* in place, single copy, two steps merged per pass (Sec. 4.1, Alg. 2) */
+    LBM_SWAP2 = 2,     /* in place, single copy, two steps merged per pass (Sec. 4.1, Alg. 2) */
+    LBM_SWAP3 = 3      /* in place, single copy, three steps merged per pass (the deeper merging the
+                          conclusion, Sec. 6, names as the next step); FP32 storage only */
 } lbm_scheme;
 
 typedef enum { LBM_PERIODIC = 0, LBM_WALL = 1, LBM_MOVING_WALL = 2 } lbm_face;
@@ -122,6 +124,7 @@ lbm_status lbm_attach(const lbm_config* cfg, void* f_dev, void* work_dev, const 
 
 /* Advance n >= 0 time steps (Sec. 3: N steps; Sec. 5.1: N/2 merged passes).
  * LBM_SWAP2 runs n/2 merged passes and, if n is odd, one single-step pass;
+ * LBM_SWAP3 runs n/3 three-step passes and one pass of the n%3 remaining steps;
  * LBM_TWO_ARRAY copies the state back into f_dev after an odd number of steps. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
@@ -199,8 +202,8 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
  * the two-array kernel) is bracketed by a pair of HIP events recorded on the
  * context's stream.  lbm_kernel_time waits for the recorded launches and
  * returns their summed duration in milliseconds and their count, split by the
- * number of steps each launch merged (index 0: one step, index 1: two steps;
- * total_ms and launches point to arrays of 2), then forgets them.  Events are
+ * number of steps each launch merged (index 0: one step, 1: two steps, 2:
+ * three steps; total_ms and launches point to arrays of 3), then forgets them.  Events are
  * host-side objects owned by the context; no device memory is allocated. */
 lbm_status lbm_set_kernel_timing(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches);

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lbm.h")
 
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_EDEVICE, LBM_ESTATE = 0, -1, -2, -3, -4
 LBM_F64, LBM_F32, LBM_F16_OFS, LBM_BF16_OFS = 0, 1, 2, 3
-LBM_TWO_ARRAY, LBM_SWAP1, LBM_SWAP2 = 0, 1, 2
+LBM_TWO_ARRAY, LBM_SWAP1, LBM_SWAP2, LBM_SWAP3 = 0, 1, 2, 3
 LBM_PERIODIC, LBM_WALL, LBM_MOVING_WALL = 0, 1, 2
 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_EDEVICE", -4: "LBM_ESTATE"}
@@ -174,11 +174,11 @@ def lbm_probe_pattern(cfg, f_dev, steps_per_pass, stream):
 
 
 def lbm_kernel_time(ctx):
-    """([ms of 1-step launches, ms of 2-step launches], [counts])"""
-    ms = (ctypes.c_double * 2)()
-    n = (ctypes.c_int64 * 2)()
+    """([ms of 1-, 2- and 3-step launches], [counts])"""
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int64 * 3)()
     _check(lib().lbm_kernel_time(ctx, ms, n), ctx)
-    return [ms[0], ms[1]], [n[0], n[1]]
+    return list(ms), list(n)
 
 
 def lbm_destroy(ctx):

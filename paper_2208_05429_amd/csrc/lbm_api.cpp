@@ -33,7 +33,7 @@ struct lbm_ctx {
     const void* force = nullptr;
     hipStream_t stream = nullptr;
     std::string err;
-    MarchPlan plan[3];  // indexed by M
+    MarchPlan plan[4];  // indexed by M
     size_t off_partials = 0, off_sums = 0, off_second = 0, off_flags = 0, off_side = 0, off_shell = 0;
     bool force_wait_timeout = false;  // test hook: every hazard wait gives up
     // measurement hook: event pairs around update-kernel launches
@@ -69,6 +69,17 @@ lbm_status fail(std::string* where, lbm_status st, const std::string& msg)
 
 bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPlan* r)
 {
+    if (M == 3) {
+        // three merged steps: the plain layout, FP32 storage (variant v takes entry v)
+        const int n3 = int(sizeof(kShapesM3F32) / sizeof(ShapeEntry));
+        if (storage != LBM_F32 || variant < 0 || variant >= n3) return false;
+        r->TY = kShapesM3F32[variant].TY;
+        r->TZ = kShapesM3F32[variant].TZ;
+        r->NT = kShapesM3F32[variant].NT;
+        r->pr = 0;
+        r->pf = 1;
+        return true;
+    }
     const ShapeEntry* tab = storage == LBM_F64 ? kShapesF64 : kShapesF32;
     const int n = storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
                                      : int(sizeof(kShapesF32) / sizeof(ShapeEntry));
@@ -98,9 +109,11 @@ bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPl
 // seam is at least as thick as the halo (or whole), in table order.
 bool plain_shape_for_seam(int storage, int M, int ny, MarchPlan* r)
 {
-    const ShapeEntry* tab = storage == LBM_F64 ? kShapesF64 : kShapesF32;
-    const int n = storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
-                                     : int(sizeof(kShapesF32) / sizeof(ShapeEntry));
+    if (M == 3 && storage != LBM_F32) return false;
+    const ShapeEntry* tab = M == 3 ? kShapesM3F32 : (storage == LBM_F64 ? kShapesF64 : kShapesF32);
+    const int n = M == 3 ? int(sizeof(kShapesM3F32) / sizeof(ShapeEntry))
+                         : (storage == LBM_F64 ? int(sizeof(kShapesF64) / sizeof(ShapeEntry))
+                                               : int(sizeof(kShapesF32) / sizeof(ShapeEntry)));
     for (int j = 0; j < n; ++j) {
         if (tab[j].pr || tab[j].M != M) continue;
         const int rem = ny % tab[j].TY;
@@ -217,7 +230,7 @@ lbm_status validate(const lbm_config* c, std::string* why)
     // the kernels address a cell within one direction's y-z plane by a 32-bit byte offset
     if ((unsigned long long)c->ny * (unsigned long long)c->nz * elem_size(c->storage) >= (1ULL << 32))
         return fail(why, LBM_EUNSUPPORTED, "one direction's y-z plane must hold less than 4 GiB (ny*nz*value size)");
-    if (c->scheme < LBM_TWO_ARRAY || c->scheme > LBM_SWAP2) return fail(why, LBM_EINVAL, "unknown scheme");
+    if (c->scheme < LBM_TWO_ARRAY || c->scheme > LBM_SWAP3) return fail(why, LBM_EINVAL, "unknown scheme");
     if (c->use_force != 0 && c->use_force != 1) return fail(why, LBM_EINVAL, "use_force must be 0 or 1");
     int moving = 0;
     for (int a = 0; a < 3; ++a) {
@@ -238,7 +251,7 @@ lbm_status validate(const lbm_config* c, std::string* why)
 }
 
 // work buffer layout; plans use the device's co-residency cap
-lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[3], size_t off[6], size_t* total, std::string* why)
+lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6], size_t* total, std::string* why)
 {
     const long long N = (long long)c.nx * c.ny * c.nz;
     size_t o = 0;
@@ -252,8 +265,10 @@ lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[3], size_t off[6
         o = align_up(o + size_t(19) * size_t(N) * elem_size(c.storage));
     } else {
         size_t flags = 0, side = 0, shell = 0;
-        for (int M = 1; M <= 2; ++M) {
-            if (M == 2 && c.scheme != LBM_SWAP2) continue;
+        // the merged schemes also run the shorter passes of a remainder of steps
+        for (int M = 1; M <= 3; ++M) {
+            if (M == 2 && c.scheme != LBM_SWAP2 && c.scheme != LBM_SWAP3) continue;
+            if (M == 3 && c.scheme != LBM_SWAP3) continue;
             lbm_status st = make_plan(c, M, cap, &plans[M], why);
             if (st != LBM_OK) return st;
             if (plans[M].flag_bytes > flags) flags = plans[M].flag_bytes;
@@ -327,7 +342,7 @@ lbm_status setup(lbm_ctx* ctx, const lbm_config* cfg, void* f_dev, void* work_de
 
     size_t off[6], total = 0, sized = 0;
     int cap = kMaxResident;
-    MarchPlan probe[3];
+    MarchPlan probe[4];
     st = layout(*cfg, cap, probe, off, &sized, why);  // what lbm_buffer_sizes reported
     if (st != LBM_OK) return st;
     if (work_cap && sized > work_cap) {
@@ -338,7 +353,7 @@ lbm_status setup(lbm_ctx* ctx, const lbm_config* cfg, void* f_dev, void* work_de
     }
     if (cfg->scheme != LBM_TWO_ARRAY) {
         // the device may hold fewer marching workgroups than the sizing bound
-        for (int M = 1; M <= 2; ++M) {
+        for (int M = 1; M <= 3; ++M) {
             if (probe[M].M == 0) continue;
             const int dc = device_cap(*cfg, probe[M]);
             if (dc <= 0) return fail(why, LBM_EDEVICE, "cannot query the co-residency of the marching kernel");
@@ -533,9 +548,13 @@ lbm_status step_n(lbm_ctx* ctx, int64_t n)
     case LBM_SWAP1:
         for (int64_t k = 0; k < n && st == LBM_OK; ++k) st = march_pass(ctx, 1, ctx->f, ctx->f);
         break;
-    default:
+    case LBM_SWAP2:
         for (int64_t k = 0; k < n / 2 && st == LBM_OK; ++k) st = march_pass(ctx, 2, ctx->f, ctx->f);
         if (st == LBM_OK && (n & 1)) st = march_pass(ctx, 1, ctx->f, ctx->f);
+        break;
+    default:
+        for (int64_t k = 0; k < n / 3 && st == LBM_OK; ++k) st = march_pass(ctx, 3, ctx->f, ctx->f);
+        if (st == LBM_OK && n % 3) st = march_pass(ctx, int(n % 3), ctx->f, ctx->f);
         break;
     }
     return st;
@@ -550,7 +569,7 @@ lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work
     std::string why;
     lbm_status st = validate(cfg, &why);
     if (st != LBM_OK) return st;
-    MarchPlan plans[3];
+    MarchPlan plans[4];
     size_t off[6], total = 0;
     st = layout(*cfg, kMaxResident, plans, off, &total, &why);
     if (st != LBM_OK) return st;
@@ -794,8 +813,8 @@ lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches)
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
     ctx->err.clear();
     if (!total_ms || !launches) return fail(&ctx->err, LBM_EINVAL, "total_ms and launches are required");
-    total_ms[0] = total_ms[1] = 0.0;
-    launches[0] = launches[1] = 0;
+    total_ms[0] = total_ms[1] = total_ms[2] = 0.0;
+    launches[0] = launches[1] = launches[2] = 0;
     if (ctx->ev_used) {
         lbm_status st = device_err(ctx, hipEventSynchronize(ctx->ev[ctx->ev_used - 1]), "event synchronize");
         if (st != LBM_OK) return st;
@@ -804,7 +823,7 @@ lbm_status lbm_kernel_time(lbm_ctx* ctx, double* total_ms, int64_t* launches)
         float ms = 0.0f;
         lbm_status st = device_err(ctx, hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]), "event elapsed time");
         if (st != LBM_OK) return st;
-        const int k = ctx->ev_steps[i / 2] == 2 ? 1 : 0;
+        const int k = ctx->ev_steps[i / 2] - 1;
         total_ms[k] += ms;
         launches[k] += 1;
     }

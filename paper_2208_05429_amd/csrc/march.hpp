@@ -1,6 +1,7 @@
-// march.hpp -- the in-place, single-copy D3Q19 update with M in {1, 2} time
+// march.hpp -- the in-place, single-copy D3Q19 update with M in {1, 2, 3} time
 // steps merged per pass over HBM (the paper's Fuse Swap LBM of Sec. 3 /
-// Alg. 1 for M = 1, and its two-step merging of Sec. 4.1 / Alg. 2 for M = 2),
+// Alg. 1 for M = 1, its two-step merging of Sec. 4.1 / Alg. 2 for M = 2, and
+// the deeper merging its conclusion (Sec. 6) names as the next step for M = 3),
 // designed for CDNA4 rather than transcribed from the CPU algorithms.
 //
 // Decomposition.  The y-z plane is cut into TY x TZ tiles and the x axis into
@@ -163,13 +164,17 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     using R = typename Cd::R;
     constexpr int WY = TY + 2 * M, WZ = TZ + 2 * M, NC = WY * WZ;
     constexpr int K = (NC + NT - 1) / NT;
-    constexpr int WZ2 = TZ + 2, NC2 = (TY + 2) * WZ2;
+    // step 2 runs on the tile plus M-1 halo cells, step 3 (M = 3) on the tile plus one
+    constexpr int WZ2 = TZ + 2 * (M - 1), NC2 = (TY + 2 * (M - 1)) * WZ2;
+    constexpr int WZ3 = TZ + 2, NC3 = (TY + 2) * WZ3;
+    constexpr int K3 = (M == 3) ? K : 1;  // step-3 registers exist for M = 3 only
     constexpr int NB1 = (M == 1) ? 2 : 1;  // a single exchange level is double-buffered
     constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
-    static_assert(M == 1 || M == 2, "one or two merged steps");
+    static_assert(M >= 1 && M <= 3, "one to three merged steps");
 
     __shared__ R X1[NB1][16 * NC];
-    __shared__ R X2[(M == 2) ? 16 * NC2 : 1];
+    __shared__ R X2[(M >= 2) ? 16 * NC2 : 1];
+    __shared__ R X3[(M == 3) ? 16 * NC3 : 1];
     __shared__ R WT[WALLS ? Q : 1];  // moving-wall terms (entry q: received along c_q)
 
     const Geom& g = a.g;
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     const long long N = g.N, PL = g.PL;
 
     // ---- columns owned by this thread ----
-    int gofs[K], rad[K], ci2[K];
+    int gofs[K], rad[K], ci2[K], ci3[K3];
     uint32_t voff[K];   // byte offset of the column within one direction's plane
     uint32_t loff[K];   // voff for columns that load (tile plus M halo cells), else out of range
     uint32_t loffR[K];  // the same in units of the arithmetic type (force field)
@@ -216,6 +221,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         voff[k] = kOffNone;
         rad[k] = M + 1;
         ci2[k] = 0;
+        if constexpr (M == 3) ci3[k] = 0;
         byz[k] = 0;
         myz[k] = 0;
         const int c = tid + k * NT;
@@ -235,6 +241,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     voff[k] = uint32_t(gofs[k]) * uint32_t(sizeof(T));
                     rad[k] = dy > dz ? dy : dz;
                     ci2[k] = (ly - 1) * WZ2 + (lz - 1);
+                    if constexpr (M == 3) ci3[k] = (ly - 2) * WZ3 + (lz - 2);
                     if constexpr (WALLS) {
                         uint32_t b = 0, mv = 0;
                         sfor<1, Q>([&](auto qc) {
@@ -279,8 +286,8 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
     // ---- pipeline registers ----
     T Lr[K][Q];
-    R Fl1[K][3], Fl2[K][3];
-    R acc1[K][Q], nxt1[K][5], acc2[K][Q], nxt2[K][5];
+    R Fl1[K][3], Fl2[K][3], Fl3[K3][3];
+    R acc1[K][Q], nxt1[K][5], acc2[K][Q], nxt2[K][5], acc3[K3][Q], nxt3[K3][5];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -288,16 +295,19 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             Lr[k][q] = T(0);
             acc1[k][q] = R(0);
             acc2[k][q] = R(0);
+            if constexpr (M == 3) acc3[k][q] = R(0);
         }
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             nxt1[k][j] = R(0);
             nxt2[k][j] = R(0);
+            if constexpr (M == 3) nxt3[k][j] = R(0);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             Fl1[k][c] = R(0);
             Fl2[k][c] = R(0);
+            if constexpr (M == 3) Fl3[k][c] = R(0);
         }
     }
 
@@ -487,16 +497,24 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     //      earlier: completes plane xl-M-1 (time t+M), stored in place after
     //      the hazard check;
     //   |  barrier, publish the load front;
-    //   E  (M = 2) receive of step 1 (completes plane xl-1 at t+1) and step-2
+    //   E  (M >= 2) receive of step 1 (completes plane xl-1 at t+1) and step-2
+    //      collide of that plane on the tile plus M-1 halo cells;
+    //   |  (M >= 2) barrier;
+    //   E3 (M = 3) receive of step 2 (completes plane xl-2 at t+2) and step-3
     //      collide of that plane on the tile plus one halo cell;
-    //   |  (M = 2) barrier.
-    // Stores leave early and the loads of the next plane have the whole of E
-    // to arrive: the first wait of the next iteration finds them done.
-    R o1[K][3], o1p[K][3], o2[K][3];
+    //   |  (M = 3) barrier.
+    // Each level's exchange is read in the phase after the one that filled it,
+    // so every level keeps its own LDS buffer.  Stores leave early and the
+    // loads of the next plane have the whole of E (and E3) to arrive: the
+    // first wait of the next iteration finds them done.
+    R o1[K][3], o1p[K][3], o2[K][3], o3[K3][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) o1[k][c] = o1p[k][c] = o2[k][c] = R(0);
+        for (int c = 0; c < 3; ++c) {
+            o1[k][c] = o1p[k][c] = o2[k][c] = R(0);
+            if constexpr (M == 3) o3[k][c] = R(0);
+        }
     if constexpr (WALLS) __syncthreads();  // the wall-term table is complete
     const int total = (e - s) + 2 * M + 1;
     issue_load(s - M, true);
@@ -545,7 +563,13 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool act = rad[k] == 0 && gofs[k] >= 0;
-                if constexpr (M == 2) {
+                if constexpr (M == 3) {
+                    if (act) complete<R, WALLS>(acc3[k], X3, NC3, ci3[k], WZ3, o3[k][1], byz[k] | xbd);
+                    store(acc3[k], k, r_out, storing);
+                    if (act)
+                        deposit<R, WALLS>(acc3[k], nxt3[k], X3, NC3, ci3[k], WZ3, o3[k][0], o3[k][1], o3[k][2],
+                                          byz[k] | xbn);
+                } else if constexpr (M == 2) {
                     if (act) complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
                     store(acc2[k], k, r_out, storing);
                     if (act)
@@ -571,10 +595,11 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         __syncthreads();
         if (tid == 0) __hip_atomic_store(a.flags + (1 + gtile) * a.fstride, i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-        if constexpr (M == 2) {
+        if constexpr (M >= 2) {
             // ---- E: step-1 receive (completes plane xl-1), step-2 collide of it ----
+            // (step 2 collides planes s-M+1 .. e+M-2: from iteration 2 on)
             const uint32_t xbd1 = xb(xl - 1), xbn1 = xb(xl), xmc2 = xm(xl - 1);
-            const bool coll2 = i >= M && present(xl - 1);
+            const bool coll2 = i >= 2 && present(xl - 1);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (rad[k] <= M - 1 && gofs[k] >= 0) {
@@ -595,9 +620,45 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, c, WZ, o1[k][0], o1[k][1], o1[k][2],
                                       byz[k] | xbn1);
                 }
-                if constexpr (FORCE) {
+                if constexpr (FORCE && M == 2) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) Fl2[k][c] = Fs[k][c];
+                }
+            }
+            if constexpr (M == 2) seen = poll_issue();
+            __syncthreads();
+        }
+        if constexpr (M == 3) {
+            // ---- E3: step-2 receive (completes plane xl-2 at t+2), step-3 collide of it ----
+            // (step 3 collides planes s-1 .. e: from iteration 4 on)
+            const uint32_t xbd2 = xb(xl - 2), xbn2 = xb(xl - 1), xmc3 = xm(xl - 2);
+            const bool coll3 = i >= 4 && present(xl - 2);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (rad[k] <= M - 2 && gofs[k] >= 0) {
+                    complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd2);
+                    if (coll3) {
+                        collide<R, FORCE>(acc2[k], omega, Fl3[k][0], Fl3[k][1], Fl3[k][2]);
+                        sfor<0, Q>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            if constexpr (moves_yz(q)) X3[yz_index(q) * NC3 + ci3[k]] = acc2[k][q];
+                        });
+                        if constexpr (WALLS)
+                            moving_wall_out(acc2[k][1], acc2[k][10], X3, NC3, ci3[k], myz[k] | xmc3, WT);
+                        o3[k][0] = acc2[k][0];
+                        o3[k][1] = acc2[k][1];
+                        o3[k][2] = acc2[k][10];
+                    }
+                    deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
+                                      byz[k] | xbn2);
+                }
+                if constexpr (FORCE) {
+                    // forces of planes xl-1 and xl move one level down
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Fl3[k][c] = Fl2[k][c];
+                        Fl2[k][c] = Fs[k][c];
+                    }
                 }
             }
             seen = poll_issue();

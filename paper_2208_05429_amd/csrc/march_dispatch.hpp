@@ -127,6 +127,9 @@ constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1,
                                      {1, 16, 64, 512, 0, 1}, {2, 32, 32, 512, 1, 1}, {1, 32, 32, 512, 1, 1},
                                      {2, 32, 32, 512, 0, 1}, {1, 32, 32, 512, 0, 1}, {2, 16, 64, 512, 1, 2},
                                      {1, 16, 64, 512, 1, 2}};
+// Three merged steps (plain layout, FP32): one frame column per thread needs
+// (TY + 6) x (TZ + 6) <= 512; variant v of LBM_SWAP3 takes entry v.
+constexpr ShapeEntry kShapesM3F32[] = {{3, 10, 26, 512, 0, 1}, {3, 16, 16, 512, 0, 1}};
 
 hipError_t launch_march_f64(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
 hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);

@@ -8,7 +8,7 @@ import torch
 from . import capi
 
 STORAGE = {"f64": capi.LBM_F64, "f32": capi.LBM_F32, "f16": capi.LBM_F16_OFS, "bf16": capi.LBM_BF16_OFS}
-SCHEME = {"two_array": capi.LBM_TWO_ARRAY, "swap1": capi.LBM_SWAP1, "swap2": capi.LBM_SWAP2}
+SCHEME = {"two_array": capi.LBM_TWO_ARRAY, "swap1": capi.LBM_SWAP1, "swap2": capi.LBM_SWAP2, "swap3": capi.LBM_SWAP3}
 FACE = {"periodic": capi.LBM_PERIODIC, "wall": capi.LBM_WALL, "moving": capi.LBM_MOVING_WALL}
 _STORE_DTYPE = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
 
@@ -31,7 +31,7 @@ class Lattice:
 
     shape    (nx, ny, nz), x slowest
     storage  'f64' | 'f32' | 'f16' | 'bf16' (the last two store f - w)
-    scheme   'two_array' | 'swap1' | 'swap2'
+    scheme   'two_array' | 'swap1' | 'swap2' | 'swap3' (FP32 only)
     faces    6 codes for -x,+x,-y,+y,-z,+z ('periodic' | 'wall' | 'moving')
     force    optional torch tensor (3, nx, ny, nz) of real_dtype(storage)
     rho0/u0  optional float64 tensors (nx,ny,nz) / (3,nx,ny,nz); None = 1 / 0

@@ -124,3 +124,12 @@ def test_null_and_state_errors():
     assert L.lbm_set_stream(None, None) == capi.LBM_ESTATE
     assert L.lbm_test_force_wait_timeout(None, 1) == capi.LBM_ESTATE
     L.lbm_destroy(None)
+
+
+def test_three_merged_steps_are_built_for_fp32_only():
+    assert _status(_cfg(scheme=capi.LBM_SWAP3))[0] == capi.LBM_OK
+    assert _status(_cfg(scheme=capi.LBM_SWAP3, variant=1))[0] == capi.LBM_OK
+    for st in (capi.LBM_F64, capi.LBM_F16_OFS, capi.LBM_BF16_OFS):
+        assert _status(_cfg(scheme=capi.LBM_SWAP3, storage=st))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(scheme=capi.LBM_SWAP3, variant=2))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(scheme=4))[0] == capi.LBM_EINVAL

@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC_Q = os.path.join(_HERE, "lbm_oracle_q.c")  # D3Q15 / D3Q19 / D3Q27, chosen at run time
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 PERIODIC, WALL, MOVING_WALL = 0, 1, 2
@@ -30,10 +31,16 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wno-unknown-pragmas",
-               "-o", tmp, _SRC, "-lm"]
+               "-o", tmp, _SRC, _SRC_Q, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+class CfgQ(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("face", ctypes.c_int32 * 6), ("wall_u", ctypes.c_double * 3),
+                ("q", ctypes.c_int32)]
 
 
 class Cfg(ctypes.Structure):
@@ -74,6 +81,18 @@ def lib():
         L.orc_collide_adjoint_cell.argtypes = [c, d, d, d, d, d]
         L.orc_adjoint_step.argtypes = [c, d, d, d, d, d]
         L.orc_adjoint_step.restype = ctypes.c_int32
+        cq = P(CfgQ)
+        L.orq_tables.argtypes = [ctypes.c_int32, P(ctypes.c_int32), d, P(ctypes.c_int32)]
+        L.orq_tables.restype = ctypes.c_int32
+        L.orq_check.argtypes = [cq]
+        L.orq_check.restype = ctypes.c_int32
+        for name, nargs in (("orq_init", 3), ("orq_collide", 3), ("orq_stream", 2), ("orq_macro", 5),
+                            ("orq_sums", 2)):
+            fn = getattr(L, name)
+            fn.argtypes = [cq] + [d] * nargs
+            fn.restype = ctypes.c_int32
+        L.orq_run.argtypes = [cq, d, d, d, ctypes.c_int64]
+        L.orq_run.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -215,3 +234,76 @@ class Oracle:
         for t in range(nsteps - 1, -1, -1):
             lam, gF = self.adjoint_step(states[t], lam, F, gF)
         return L, gF
+
+
+# --------------------------------------------------------------------------
+# D3Q15 / D3Q19 / D3Q27 (lbm_oracle_q.c)
+# --------------------------------------------------------------------------
+
+def tables_q(q):
+    """(c[Q,3] int, w[Q] float64, opp[Q] int) of velocity set q (15, 19 or 27)."""
+    c = np.zeros((27, 3), np.int32)
+    w = np.zeros(27, np.float64)
+    opp = np.zeros(27, np.int32)
+    n = lib().orq_tables(int(q), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _p(w),
+                         opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if n < 0:
+        raise ValueError(f"no velocity set D3Q{q}")
+    return c[:n], w[:n], opp[:n]
+
+
+class OracleQ(Oracle):
+    """Oracle over velocity set ``q`` (15, 19 or 27): init, run, collide,
+    stream, macro and sums as ``Oracle`` (no adjoint)."""
+
+    def __init__(self, shape, tau, q, faces=(PERIODIC,) * 6, wall_u=(0.0, 0.0, 0.0)):
+        self.shape = tuple(int(s) for s in shape)
+        self.N = int(np.prod(self.shape))
+        self.Q = int(q)
+        self.cfg = CfgQ(self.shape[0], self.shape[1], self.shape[2], float(tau),
+                        (ctypes.c_int32 * 6)(*faces), (ctypes.c_double * 3)(*wall_u), int(q))
+        _chk(lib().orq_check(ctypes.byref(self.cfg)), "configuration")
+
+    def init(self, rho0=None, u0=None):
+        f = np.zeros(self._fshape(self.Q))
+        r = None if rho0 is None else np.ascontiguousarray(rho0, np.float64)
+        u = None if u0 is None else np.ascontiguousarray(u0, np.float64)
+        _chk(lib().orq_init(ctypes.byref(self.cfg), _p(r), _p(u), _p(f)), "init")
+        return f
+
+    def run(self, f, nsteps, F=None):
+        f = np.array(f, np.float64, order="C", copy=True)
+        tmp = np.empty_like(f)
+        Fa = None if F is None else np.ascontiguousarray(F, np.float64)
+        _chk(lib().orq_run(ctypes.byref(self.cfg), _p(Fa), _p(f), _p(tmp), int(nsteps)), "run")
+        return f
+
+    def collide(self, f, F=None):
+        f = np.ascontiguousarray(f, np.float64)
+        out = np.empty_like(f)
+        Fa = None if F is None else np.ascontiguousarray(F, np.float64)
+        _chk(lib().orq_collide(ctypes.byref(self.cfg), _p(Fa), _p(f), _p(out)), "collide")
+        return out
+
+    def stream(self, fpost):
+        fpost = np.ascontiguousarray(fpost, np.float64)
+        out = np.empty_like(fpost)
+        _chk(lib().orq_stream(ctypes.byref(self.cfg), _p(fpost), _p(out)), "stream")
+        return out
+
+    def macro(self, f, F=None):
+        f = np.ascontiguousarray(f, np.float64)
+        rho = np.empty(self.shape)
+        u = np.empty(self._fshape(3))
+        un = np.empty(self.shape)
+        Fa = None if F is None else np.ascontiguousarray(F, np.float64)
+        _chk(lib().orq_macro(ctypes.byref(self.cfg), _p(Fa), _p(f), _p(rho), _p(u), _p(un)), "macro")
+        return rho, u, un
+
+    def sums(self, f):
+        out = np.zeros(4)
+        _chk(lib().orq_sums(ctypes.byref(self.cfg), _p(np.ascontiguousarray(f, np.float64)), _p(out)), "sums")
+        return out
+
+    def collide_adjoint_cell(self, *a, **k):
+        raise NotImplementedError("the generic-lattice oracle has no adjoint")

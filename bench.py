@@ -46,6 +46,8 @@ def parse():
                          "state)")
     ap.add_argument("--shape", default=None, metavar="NXxNYxNZ", help="a lattice of this shape instead of --size cubed")
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--velocities", type=int, default=19, choices=[15, 19, 27],
+                    help="velocity set (D3Q15 and D3Q27: FP64/FP32 storage, planes of one round)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=24.0, help="target length of the oracle sample (the estimate from a short timing runs long, so the sample lands near 10-20 s)")
     ap.add_argument("--copy-probe", type=int, default=1 << 31, metavar="BYTES",
@@ -319,33 +321,33 @@ def main():
     if a.workload == "cavity":
         tau = wl.CAVITY_256["tau"]
         lat = Lattice(shape, tau, a.storage, a.scheme, ("wall", "wall", "wall", "moving", "wall", "wall"),
-                      (wl.CAVITY_256["lid_u"], 0.0, 0.0), variant=a.variant)
-        wdesc = (f"{sname} lid-driven cavity D3Q19 BGK tau={tau}, halfway bounce-back on 5 walls, +y lid "
+                      (wl.CAVITY_256["lid_u"], 0.0, 0.0), variant=a.variant, velocities=a.velocities)
+        wdesc = (f"{sname} lid-driven cavity D3Q{a.velocities} BGK tau={tau}, halfway bounce-back on 5 walls, +y lid "
                  f"u=({wl.CAVITY_256['lid_u']},0,0), rest state, {a.storage} storage")
     elif a.workload == "large":
         cfg = wl.TGV_1024
         tau = cfg["tau"]
         u0_dev = wl.taylor_green_3d_device(shape, cfg["u0"], wl.random_phases(cfg["phase_seed"]), "cuda")
-        lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
+        lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant, velocities=a.velocities)
         del u0_dev
-        wdesc = (f"{sname} periodic D3Q19 BGK tau={tau}, random-phase Taylor-Green u0={cfg['u0']} (seed "
+        wdesc = (f"{sname} periodic D3Q{a.velocities} BGK tau={tau}, random-phase Taylor-Green u0={cfg['u0']} (seed "
                  f"{cfg['phase_seed']}), {a.storage} storage")
     elif a.workload == "channel":
         tau = 0.8
         F = torch.from_numpy(wl.normal_field(shape, 1e-6, 1)).to(torch.float64 if a.storage == "f64" else torch.float32)
         lat = Lattice(shape, tau, a.storage, a.scheme, ("periodic", "periodic", "wall", "wall", "wall", "wall"),
-                      force=F.cuda(), variant=a.variant)
+                      force=F.cuda(), variant=a.variant, velocities=a.velocities)
         del F
-        wdesc = (f"{sname} channel D3Q19 BGK tau={tau}, periodic x, bounce-back walls in y and z, per-cell body "
+        wdesc = (f"{sname} channel D3Q{a.velocities} BGK tau={tau}, periodic x, bounce-back walls in y and z, per-cell body "
                  f"force N(0, 1e-12) (seed 1), rest state, {a.storage} storage")
     else:
         tau = wl.TGV_512["tau"]
         _, u0 = wl.tgv_512_fields(shape)
         u0_dev = torch.from_numpy(u0).to("cuda")
         del u0
-        lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant)
+        lat = Lattice(shape, tau, a.storage, a.scheme, u0=u0_dev, variant=a.variant, velocities=a.velocities)
         del u0_dev
-        wdesc = (f"{sname} periodic D3Q19 BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
+        wdesc = (f"{sname} periodic D3Q{a.velocities} BGK tau={tau}, Taylor-Green u0=0.02 + U(+-1e-3) noise "
                  f"(seed 20805429), {a.storage} storage")
     torch.cuda.empty_cache()
     print(f"[bench] warmup {a.warmup} steps", file=sys.stderr, flush=True)
@@ -378,7 +380,8 @@ def main():
     k = M - 1
     avg_kernel_ms = kms[k] / max(kn[k], 1)
     s = BYTES[a.storage]
-    alg_bytes = 2 * 19 * s * N  # one read and one write of the single copy per launch
+    Qv = a.velocities
+    alg_bytes = 2 * Qv * s * N  # one read and one write of the single copy per launch
     achieved = alg_bytes / (avg_kernel_ms * 1e-3) / 1e9
     kernel_key = (f"march_M{M}_{a.storage}_{a.size}" if a.scheme != "two_array" else f"two_array_{a.storage}_{a.size}")
     if a.variant:
@@ -387,6 +390,8 @@ def main():
         kernel_key += "_" + sname
     if a.workload != "tgv":
         kernel_key += "_" + a.workload
+    if Qv != 19:
+        kernel_key += f"_q{Qv}"
     traffic = traffic_entry(kernel_key)
     out = {
         "metric": METRIC,
@@ -403,7 +408,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wdesc,
                    "scheme": a.scheme, "steps_per_launch": M, "variant": a.variant,
-                   "bytes_per_lattice_update": 2 * 19 * s / M},
+                   "bytes_per_lattice_update": 2 * Qv * s / M},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_march" if a.scheme != "two_array" else "k_two_array",
@@ -420,8 +425,8 @@ def main():
             msr = kms[m - 1] / kn[m - 1]
             out["roofline"][f"remainder_launch_{m}_steps"] = {
                 "launches": kn[m - 1], "avg_kernel_ms": round(msr, 4),
-                "achieved": round(2 * 19 * s * N / (msr * 1e-3) / 1e9, 1)}
-    if a.copy_probe and a.scheme != "two_array" and a.storage != "f64" and shape[2] % 2 == 0:
+                "achieved": round(2 * Qv * s * N / (msr * 1e-3) / 1e9, 1)}
+    if a.copy_probe and a.scheme != "two_array" and a.storage != "f64" and shape[2] % 2 == 0 and Qv == 19:
         # the kernel's access pattern without its compute (the library's
         # pattern probe: same work items and pair accesses, no halo, no LDS,
         # no hazard checks; it stores back what it loaded)
@@ -477,7 +482,8 @@ def main():
             out["pattern_probe"]["frac_of_copy"] = round(out["pattern_probe"]["gbs"] / copy_gbs, 4)
         del src, dst
         torch.cuda.empty_cache()
-    headline = a.storage == "f32" and a.scheme == "swap2" and a.workload == "tgv" and a.shape is None
+    headline = (a.storage == "f32" and a.scheme == "swap2" and a.workload == "tgv" and a.shape is None
+                and Qv == 19)
     if headline and not a.no_storage_sweep:
         print("[bench] FP16/BF16 storage runs", file=sys.stderr, flush=True)
         sw = storage_sweep(a.size, 40)

@@ -12,6 +12,12 @@
  *           (-1,1,0) (-1,0,-1) (-1,0,1) (0,-1,-1) (0,-1,1); c_{q+9} = -c_q
  *           (directions 1..9 are the neighbours that precede a cell in an
  *           x-slowest, z-fastest sweep, Sec. 3).  Weights 1/3, 1/18, 1/36.
+ *           With lbm_config.velocities, the other two cubic sets (Q values
+ *           per cell, c_{q+H} = -c_q, H = (Q-1)/2, c_1..c_H preceding):
+ *           D3Q15  c_1..c_7 = (-1,0,0) (0,-1,0) (0,0,-1) (-1,-1,-1) (-1,-1,1)
+ *                  (-1,1,-1) (-1,1,1); weights 2/9, 1/9, 1/72 by |c|^2 = 0, 1, 3.
+ *           D3Q27  c_1..c_9 as D3Q19, c_10..c_13 = (-1,-1,-1) (-1,-1,1)
+ *                  (-1,1,-1) (-1,1,1); weights 8/27, 2/27, 1/54, 1/216.
  * Model     BGK with relaxation time tau (> 1/2); rho = sum f,
  *           u = (sum c f + F/2)/rho; second-order equilibrium; Guo forcing
  *           when a body-force field F is attached; halfway bounce-back on wall
@@ -21,7 +27,8 @@
  *           distribution buffer holds the post-stream state of the last step,
  *           in natural layout: slot q of cell x holds f_q(x).
  * Layout    f[q][x][y][z], z fastest: element q*N + (x*ny + y)*nz + z with
- *           N = nx*ny*nz; the stored value is the offset g = f - w_q, in the
+ *           N = nx*ny*nz (q < Q, the set's size; 19 unless stated); the
+ *           stored value is the offset g = f - w_q, in the
  *           storage type of the configuration.  Vector fields (u, F, their
  *           gradients) are SoA: a[c*N + cell], c = 0 (x), 1 (y), 2 (z).
  * Memory    every pointer named *_dev is device memory owned by the caller
@@ -89,6 +96,9 @@ typedef struct {
     double wall_u[3];   /* velocity of the moving-wall face (ignored without one) */
     int32_t use_force;  /* 1: a body-force density field F (3N, double for LBM_F64, float otherwise) */
     int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes */
+    int32_t velocities; /* velocity set: 0 or 19 = D3Q19 (the paper's); 15 = D3Q15, 27 = D3Q27 (Sec. 4.1 names
+                           both as sets the two-step rule holds for): FP64 and FP32 storage, LBM_TWO_ARRAY,
+                           LBM_SWAP1 and LBM_SWAP2, planes that fit one round, no adjoint or probes */
 } lbm_config;
 
 /* Bytes the caller must provide for the distribution buffer (19*N values of

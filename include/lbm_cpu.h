@@ -30,9 +30,9 @@
  *            g_q = f_q - w_q (FP64).  After any call the array holds the
  *            post-stream state: slot q of a cell holds f_q - w_q.
  * Config     the lbm_config of include/lbm.h; storage, scheme and variant are
- *            ignored; use_force must be 0.  lbm_cpu_two_step needs a wall
- *            (or moving wall) on every face, as the lid-driven cavity of
- *            Sec. 5.1 has.
+ *            ignored; use_force must be 0 and velocities 0 or 19 (D3Q19).
+ *            lbm_cpu_two_step needs a wall (or moving wall) on every face, as
+ *            the lid-driven cavity of Sec. 5.1 has.
  * Errors     LBM_EINVAL for a bad configuration or a NULL pointer,
  *            LBM_EUNSUPPORTED for what is not built (a body force; periodic
  *            faces in the two-step sweep); nothing aborts.  The array is

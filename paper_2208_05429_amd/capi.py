@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EUNSUPPORTED", -3: "LBM_
 class lbm_config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("scheme", ctypes.c_int32), ("face", ctypes.c_int32 * 6),
-                ("wall_u", ctypes.c_double * 3), ("use_force", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("wall_u", ctypes.c_double * 3), ("use_force", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("velocities", ctypes.c_int32)]
 
 
 class LbmError(RuntimeError):
@@ -81,10 +82,10 @@ def header_functions():
 
 
 def make_config(shape, tau, storage=LBM_F32, scheme=LBM_SWAP2, faces=(LBM_PERIODIC,) * 6, wall_u=(0.0, 0.0, 0.0),
-                use_force=False, variant=0):
+                use_force=False, variant=0, velocities=19):
     return lbm_config(int(shape[0]), int(shape[1]), int(shape[2]), float(tau), int(storage), int(scheme),
                       (ctypes.c_int32 * 6)(*[int(f) for f in faces]), (ctypes.c_double * 3)(*[float(v) for v in wall_u]),
-                      1 if use_force else 0, int(variant))
+                      1 if use_force else 0, int(variant), int(velocities))
 
 
 def _check(status, ctx=None):

@@ -2,6 +2,7 @@
 // the marching-pass prepass, macroscopic fields with FP64 conservation sums,
 // and the storage-type dispatch of every launcher.
 #include "d3q19.hpp"
+#include "lattices.hpp"
 #include "lbm_internal.hpp"
 
 namespace lbm {
@@ -10,7 +11,7 @@ namespace lbm {
 // f := f_eq(rho0, u0), stored as g = f - w (Sec. 5.1: every algorithm starts
 // from the same constructed state).  Evaluated in double, rounded once.
 // ------------------------------------------------------------------------
-template <int S>
+template <class LT, int S>
 __global__ __launch_bounds__(256) void k_init(Geom g, typename Codec<S>::T* f, const double* rho0, const double* u0)
 {
     using Cd = Codec<S>;
@@ -20,10 +21,10 @@ __global__ __launch_bounds__(256) void k_init(Geom g, typename Codec<S>::T* f, c
     const double rho = rho0 ? rho0[i] : 1.0;
     const double ux = u0 ? u0[i] : 0.0, uy = u0 ? u0[g.N + i] : 0.0, uz = u0 ? u0[2 * g.N + i] : 0.0;
     const double usq = ux * ux + uy * uy + uz * uz;
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const double cu = cxq(q) * ux + cyq(q) * uy + czq(q) * uz;
-        const double geq = wq<double>(q) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+        const double cu = LT::cx(q) * ux + LT::cy(q) * uy + LT::cz(q) * uz;
+        const double geq = LT::template w<double>(q) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
         f[q * g.N + i] = Cd::enc(R(geq));
     });
 }
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(256) void k_init(Geom g, typename Codec<S>::T* f, c
 // lattice), one thread per cell.  Same per-cell arithmetic as the in-place
 // kernels, so the three schemes agree to the last bit.
 // ------------------------------------------------------------------------
-template <int S, bool WALLS, bool FORCE>
+template <class LT, int S, bool WALLS, bool FORCE>
 __global__ __launch_bounds__(256) void k_two_array(Geom g, const typename Codec<S>::T* __restrict__ src,
                                                    typename Codec<S>::T* __restrict__ dst,
                                                    const typename Codec<S>::R* __restrict__ F)
@@ -45,20 +46,20 @@ __global__ __launch_bounds__(256) void k_two_array(Geom g, const typename Codec<
     const int z = int(i % g.nz);
     const long long r = i / g.nz;
     const int y = int(r % g.ny), x = int(r / g.ny);
-    R v[Q];
+    R v[LT::Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(src[q * g.N + i]);
+    for (int q = 0; q < LT::Q; ++q) v[q] = Cd::dec(src[q * g.N + i]);
     R Fx = R(0), Fy = R(0), Fz = R(0);
     if constexpr (FORCE) {
         Fx = F[i];
         Fy = F[g.N + i];
         Fz = F[2 * g.N + i];
     }
-    collide<R, FORCE>(v, R(g.omega), Fx, Fy, Fz);
+    LT::template collide<R, FORCE>(v, R(g.omega), Fx, Fy, Fz);
     const int n[3] = {g.nx, g.ny, g.nz};
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const int c[3] = {cxq(q), cyq(q), czq(q)};
+        const int c[3] = {LT::cx(q), LT::cy(q), LT::cz(q)};
         int p[3] = {x + c[0], y + c[1], z + c[2]};
         bool out = false, moving = false;
 #pragma unroll
@@ -74,8 +75,8 @@ __global__ __launch_bounds__(256) void k_two_array(Geom g, const typename Codec<
         }
         if (WALLS && out) {
             R val = v[q];
-            if (moving) val += wall_term<oppq(q)>(R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
-            dst[oppq(q) * g.N + i] = Cd::enc(val);
+            if (moving) val += wall_term_l<LT, LT::opp(q)>(R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+            dst[LT::opp(q) * g.N + i] = Cd::enc(val);
         } else {
             dst[q * g.N + ((long long)p[0] * g.ny + p[1]) * g.nz + p[2]] = Cd::enc(v[q]);
         }
@@ -91,7 +92,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_prepass(Geom g, const T* __restrict__ f, T* __restrict__ side, int* flags,
                                                  int nflags, int fstride, int M, int seg_len, int nseg)
 {
-    const long long per = (long long)Q * g.PL;
+    const long long per = (long long)g.lat * g.PL;
     const long long total = (long long)nseg * M * per;
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
         const long long bj = t / per, rem = t - bj * per;
@@ -135,7 +136,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
     return t;
 }
 
-template <int S, bool FORCE>
+template <class LT, int S, bool FORCE>
 __global__ __launch_bounds__(256) void k_macro(Geom g, const typename Codec<S>::T* __restrict__ f,
                                                const typename Codec<S>::R* __restrict__ F, double* rho_out,
                                                double* u_out, double* un_out, double* partials)
@@ -144,16 +145,16 @@ __global__ __launch_bounds__(256) void k_macro(Geom g, const typename Codec<S>::
     __shared__ double sh[4];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < g.N; i += (long long)gridDim.x * 256) {
-        double gq[Q];
+        double gq[LT::Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) gq[q] = double(Cd::dec(f[q * g.N + i]));
+        for (int q = 0; q < LT::Q; ++q) gq[q] = double(Cd::dec(f[q * g.N + i]));
         double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        sfor<0, Q>([&](auto qc) {
+        sfor<0, LT::Q>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             drho += gq[q];
-            if constexpr (cxq(q) != 0) jx += cxq(q) * gq[q];
-            if constexpr (cyq(q) != 0) jy += cyq(q) * gq[q];
-            if constexpr (czq(q) != 0) jz += czq(q) * gq[q];
+            if constexpr (LT::cx(q) != 0) jx += LT::cx(q) * gq[q];
+            if constexpr (LT::cy(q) != 0) jy += LT::cy(q) * gq[q];
+            if constexpr (LT::cz(q) != 0) jz += LT::cz(q) * gq[q];
         });
         acc[0] += drho;
         acc[1] += jx;
@@ -201,26 +202,39 @@ __global__ __launch_bounds__(256) void k_sums(const double* partials, int nblock
 // ------------------------------------------------------------------------
 static unsigned grid_for(long long n) { return unsigned((n + 255) / 256); }
 
-template <int S>
+template <class LT, int S>
 static hipError_t init_s(const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init<S>, dim3(grid_for(g.N)), dim3(256), 0, s, g, static_cast<typename Codec<S>::T*>(f),
-                       rho0, u0);
+    hipLaunchKernelGGL((k_init<LT, S>), dim3(grid_for(g.N)), dim3(256), 0, s, g,
+                       static_cast<typename Codec<S>::T*>(f), rho0, u0);
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s)
+// D3Q15 and D3Q27 are built for FP64 and FP32 storage
+template <class LT>
+static hipError_t init_set(int storage, const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s)
 {
     switch (storage) {
-    case ST_F64: return init_s<ST_F64>(g, f, rho0, u0, s);
-    case ST_F32: return init_s<ST_F32>(g, f, rho0, u0, s);
-    case ST_F16: return init_s<ST_F16>(g, f, rho0, u0, s);
-    case ST_BF16: return init_s<ST_BF16>(g, f, rho0, u0, s);
+    case ST_F64: return init_s<LT, ST_F64>(g, f, rho0, u0, s);
+    case ST_F32: return init_s<LT, ST_F32>(g, f, rho0, u0, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int S, bool FORCE>
+hipError_t launch_init(int storage, const Geom& g, void* f, const double* rho0, const double* u0, hipStream_t s)
+{
+    if (g.lat == 15) return init_set<D3Q15>(storage, g, f, rho0, u0, s);
+    if (g.lat == 27) return init_set<D3Q27>(storage, g, f, rho0, u0, s);
+    switch (storage) {
+    case ST_F64: return init_s<D3Q19, ST_F64>(g, f, rho0, u0, s);
+    case ST_F32: return init_s<D3Q19, ST_F32>(g, f, rho0, u0, s);
+    case ST_F16: return init_s<D3Q19, ST_F16>(g, f, rho0, u0, s);
+    case ST_BF16: return init_s<D3Q19, ST_BF16>(g, f, rho0, u0, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int S, bool FORCE, class LT = D3Q19>
 static hipError_t two_array_s(const Geom& g, const void* src, void* dst, const void* F, hipStream_t s)
 {
     using Cd = Codec<S>;
@@ -229,15 +243,30 @@ static hipError_t two_array_s(const Geom& g, const void* src, void* dst, const v
     auto dp = static_cast<typename Cd::T*>(dst);
     auto fp = static_cast<const typename Cd::R*>(F);
     if (walls)
-        hipLaunchKernelGGL((k_two_array<S, true, FORCE>), dim3(grid_for(g.N)), dim3(256), 0, s, g, sp, dp, fp);
+        hipLaunchKernelGGL((k_two_array<LT, S, true, FORCE>), dim3(grid_for(g.N)), dim3(256), 0, s, g, sp, dp, fp);
     else
-        hipLaunchKernelGGL((k_two_array<S, false, FORCE>), dim3(grid_for(g.N)), dim3(256), 0, s, g, sp, dp, fp);
+        hipLaunchKernelGGL((k_two_array<LT, S, false, FORCE>), dim3(grid_for(g.N)), dim3(256), 0, s, g, sp, dp, fp);
     return hipGetLastError();
+}
+
+template <class LT>
+static hipError_t two_array_set(int storage, bool force, const Geom& g, const void* src, void* dst, const void* F,
+                                hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64:
+        return force ? two_array_s<ST_F64, true, LT>(g, src, dst, F, s) : two_array_s<ST_F64, false, LT>(g, src, dst, F, s);
+    case ST_F32:
+        return force ? two_array_s<ST_F32, true, LT>(g, src, dst, F, s) : two_array_s<ST_F32, false, LT>(g, src, dst, F, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_two_array(int storage, bool force, const Geom& g, const void* src, void* dst, const void* F,
                             hipStream_t s)
 {
+    if (g.lat == 15) return two_array_set<D3Q15>(storage, force, g, src, dst, F, s);
+    if (g.lat == 27) return two_array_set<D3Q27>(storage, force, g, src, dst, F, s);
     switch (storage) {
     case ST_F64: return force ? two_array_s<ST_F64, true>(g, src, dst, F, s) : two_array_s<ST_F64, false>(g, src, dst, F, s);
     case ST_F32: return force ? two_array_s<ST_F32, true>(g, src, dst, F, s) : two_array_s<ST_F32, false>(g, src, dst, F, s);
@@ -250,13 +279,13 @@ hipError_t launch_two_array(int storage, bool force, const Geom& g, const void* 
 hipError_t launch_copy(int storage, const Geom& g, const void* src, void* dst, hipStream_t s)
 {
     const size_t elem = storage == ST_F64 ? 8 : (storage == ST_F32 ? 4 : 2);
-    return hipMemcpyAsync(dst, src, size_t(Q) * size_t(g.N) * elem, hipMemcpyDeviceToDevice, s);
+    return hipMemcpyAsync(dst, src, size_t(g.lat) * size_t(g.N) * elem, hipMemcpyDeviceToDevice, s);
 }
 
 template <class T>
 static hipError_t prepass_t(const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags, hipStream_t s)
 {
-    const long long total = (long long)p.nseg * p.M * Q * g.PL;
+    const long long total = (long long)p.nseg * p.M * g.lat * g.PL;
     long long blocks = (total + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 16384) blocks = 16384;
@@ -274,15 +303,15 @@ __global__ __launch_bounds__(256) void k_shells(Geom g, const T* __restrict__ f,
                                                 int band_rows, int nbands)
 {
     const long long rowlen = (long long)M * g.nz;
-    const long long total = (long long)nbands * 2 * g.nx * Q * rowlen;
+    const long long total = (long long)nbands * 2 * g.nx * g.lat * rowlen;
     for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
         long long r = t;
         const int z = int(r % g.nz);
         r /= g.nz;
         const int row = int(r % M);
         r /= M;
-        const int q = int(r % Q);
-        r /= Q;
+        const int q = int(r % g.lat);
+        r /= g.lat;
         const int x = int(r % g.nx);
         r /= g.nx;
         const int part = int(r % 2), band = int(r / 2);
@@ -295,7 +324,7 @@ __global__ __launch_bounds__(256) void k_shells(Geom g, const T* __restrict__ f,
 template <class T>
 static hipError_t shells_t(const Geom& g, const MarchPlan& p, int TY, const void* f, void* shell, hipStream_t s)
 {
-    const long long total = (long long)p.nbands * 2 * g.nx * Q * p.M * g.nz;
+    const long long total = (long long)p.nbands * 2 * g.nx * g.lat * p.M * g.nz;
     long long blocks = (total + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_shells<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
@@ -323,12 +352,12 @@ hipError_t launch_prepass(int storage, const Geom& g, const MarchPlan& p, const 
     }
 }
 
-template <int S, bool FORCE>
+template <int S, bool FORCE, class LT = D3Q19>
 static hipError_t macro_s(const Geom& g, const void* f, const void* F, double* rho, double* u, double* un,
                           double* partials, double* sums, hipStream_t s)
 {
     using Cd = Codec<S>;
-    hipLaunchKernelGGL((k_macro<S, FORCE>), dim3(SUM_BLOCKS), dim3(256), 0, s, g,
+    hipLaunchKernelGGL((k_macro<LT, S, FORCE>), dim3(SUM_BLOCKS), dim3(256), 0, s, g,
                        static_cast<const typename Cd::T*>(f), static_cast<const typename Cd::R*>(F), rho, u, un,
                        sums ? partials : nullptr);
     hipError_t e = hipGetLastError();
@@ -337,9 +366,26 @@ static hipError_t macro_s(const Geom& g, const void* f, const void* F, double* r
     return hipGetLastError();
 }
 
+template <class LT>
+static hipError_t macro_set(int storage, bool force, const Geom& g, const void* f, const void* F, double* rho,
+                            double* u, double* unorm, double* partials, double* sums, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64:
+        return force ? macro_s<ST_F64, true, LT>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_F64, false, LT>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_F32:
+        return force ? macro_s<ST_F32, true, LT>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_F32, false, LT>(g, f, F, rho, u, unorm, partials, sums, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_macro(int storage, bool force, const Geom& g, const void* f, const void* F, double* rho, double* u,
                         double* unorm, double* partials, double* sums, hipStream_t s)
 {
+    if (g.lat == 15) return macro_set<D3Q15>(storage, force, g, f, F, rho, u, unorm, partials, sums, s);
+    if (g.lat == 27) return macro_set<D3Q27>(storage, force, g, f, F, rho, u, unorm, partials, sums, s);
     switch (storage) {
     case ST_F64:
         return force ? macro_s<ST_F64, true>(g, f, F, rho, u, unorm, partials, sums, s)

@@ -58,6 +58,8 @@ constexpr size_t kAlign = 256;
 constexpr int kFlagStride = 1024;  // ints (4 KB)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+// the velocity set: 19 (the default, also for 0), 15 or 27
+int lat_of(const lbm_config& c) { return c.velocities == 0 ? 19 : c.velocities; }
 size_t elem_size(int storage) { return storage == LBM_F64 ? 8 : (storage == LBM_F32 ? 4 : 2); }
 size_t real_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
@@ -67,8 +69,23 @@ lbm_status fail(std::string* where, lbm_status st, const std::string& msg)
     return st;
 }
 
-bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPlan* r)
+bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPlan* r, int lat = 19)
 {
+    if (lat != 19) {
+        // D3Q15 / D3Q27: one shape per storage and step count
+        if (variant != 0 || M > 2) return false;
+        for (const SetShapes& e : kSetShapes)
+            if (e.lat == lat && e.storage == storage) {
+                const ShapeEntry& t = M == 2 ? e.m2 : e.m1;
+                r->TY = t.TY;
+                r->TZ = t.TZ;
+                r->NT = t.NT;
+                r->pr = 0;
+                r->pf = 1;
+                return true;
+            }
+        return false;
+    }
     if (M == 3) {
         // three merged steps: the plain layout, FP32 storage (variant v takes entry v)
         const int n3 = int(sizeof(kShapesM3F32) / sizeof(ShapeEntry));
@@ -133,7 +150,8 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
 {
     MarchPlan r;
     r.M = M;
-    if (!march_shape_of(c.storage, M, c.variant, c.nz, false, &r))
+    const int lat = lat_of(c);
+    if (!march_shape_of(c.storage, M, c.variant, c.nz, false, &r, lat))
         return fail(why, LBM_EUNSUPPORTED, "no compiled marching kernel for this storage/variant");
     const bool py = c.face[2] == LBM_PERIODIC, pz = c.face[4] == LBM_PERIODIC;
     r.nty = (c.ny + r.TY - 1) / r.TY;
@@ -162,6 +180,10 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     const int tiles = r.nty * r.ntz;
     r.nbands = 1;
     r.nty_band = r.nty;
+    if (tiles > cap && lat != 19)
+        return fail(why, LBM_EUNSUPPORTED,
+                    "the y-z plane needs more marching workgroups than can be co-resident; rounds over bands of tile "
+                    "rows are built for D3Q19 only");
     if (tiles > cap) {
         // rounds over bands of tile rows, each band's boundary rows saved first
         auto need = [&]() {
@@ -209,7 +231,7 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     r.blocks = tiles_run * nseg;
     r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
     r.cap = cap;
-    r.side_bytes = size_t(nseg) * size_t(M) * 19u * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
+    r.side_bytes = size_t(nseg) * size_t(M) * size_t(lat) * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
     r.shell_bytes = r.nbands > 1 ? size_t(r.nbands) * 2u * size_t(M) * size_t(c.nz) * size_t(c.nx) * 19u *
                                        elem_size(c.storage)
                                  : 0;
@@ -247,6 +269,12 @@ lbm_status validate(const lbm_config* c, std::string* why)
     if (c->use_force && c->storage != LBM_F64 && c->storage != LBM_F32)
         return fail(why, LBM_EUNSUPPORTED, "a body force is built for FP64 and FP32 storage only");
     if (c->variant < 0) return fail(why, LBM_EINVAL, "variant must be >= 0");
+    if (c->velocities != 0 && c->velocities != 15 && c->velocities != 19 && c->velocities != 27)
+        return fail(why, LBM_EINVAL, "velocities must be 0 (D3Q19), 15, 19 or 27");
+    if (lat_of(*c) != 19 && c->storage != LBM_F64 && c->storage != LBM_F32)
+        return fail(why, LBM_EUNSUPPORTED, "D3Q15 and D3Q27 are built for FP64 and FP32 storage only");
+    if (lat_of(*c) != 19 && c->scheme == LBM_SWAP3)
+        return fail(why, LBM_EUNSUPPORTED, "three merged steps are built for D3Q19 only");
     return LBM_OK;
 }
 
@@ -262,7 +290,7 @@ lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6
     off[2] = off[3] = off[4] = off[5] = 0;
     if (c.scheme == LBM_TWO_ARRAY) {
         off[2] = o;  // the second lattice of the plain scheme
-        o = align_up(o + size_t(19) * size_t(N) * elem_size(c.storage));
+        o = align_up(o + size_t(lat_of(c)) * size_t(N) * elem_size(c.storage));
     } else {
         size_t flags = 0, side = 0, shell = 0;
         // the merged schemes also run the shorter passes of a remainder of steps
@@ -299,6 +327,7 @@ int device_cap(const lbm_config& c, const MarchPlan& p)
 {
     const bool walls = c.face[0] != LBM_PERIODIC || c.face[2] != LBM_PERIODIC || c.face[4] != LBM_PERIODIC;
     const bool force = c.use_force != 0;
+    if (lat_of(c) != 19) return max_blocks_set(lat_of(c), c.storage, walls, force, p);
     switch (c.storage) {
     case LBM_F64: return max_blocks_f64(walls, force, p);
     case LBM_F32: return max_blocks_f32(walls, force, p);
@@ -339,6 +368,7 @@ lbm_status setup(lbm_ctx* ctx, const lbm_config* cfg, void* f_dev, void* work_de
     for (int fc = 0; fc < 6; ++fc)
         if (cfg->face[fc] == LBM_MOVING_WALL) g.moving_face = fc;
     g.omega = 1.0 / cfg->tau;
+    g.lat = lat_of(*cfg);
 
     size_t off[6], total = 0, sized = 0;
     int cap = kMaxResident;
@@ -489,6 +519,10 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
         pb.blocks = padded <= p.cap ? padded : a.items;
         pb.xcd_remap = (pb.blocks % 8 == 0) ? 1 : 0;
         a.xcd_remap = pb.xcd_remap;
+        if (ctx->g.lat != 19) {
+            e = launch_march_set(ctx->g.lat, ctx->cfg.storage, walls, force, pb, a, ctx->stream);
+            continue;
+        }
         switch (ctx->cfg.storage) {
         case LBM_F64: e = launch_march_f64(walls, force, pb, a, ctx->stream); break;
         case LBM_F32: e = launch_march_f32(walls, force, pb, a, ctx->stream); break;
@@ -573,7 +607,8 @@ lbm_status lbm_buffer_sizes(const lbm_config* cfg, size_t* f_bytes, size_t* work
     size_t off[6], total = 0;
     st = layout(*cfg, kMaxResident, plans, off, &total, &why);
     if (st != LBM_OK) return st;
-    if (f_bytes) *f_bytes = size_t(19) * size_t(cfg->nx) * size_t(cfg->ny) * size_t(cfg->nz) * elem_size(cfg->storage);
+    if (f_bytes)
+        *f_bytes = size_t(lat_of(*cfg)) * size_t(cfg->nx) * size_t(cfg->ny) * size_t(cfg->nz) * elem_size(cfg->storage);
     if (work_bytes) *work_bytes = total;
     return LBM_OK;
 }
@@ -657,7 +692,7 @@ lbm_status lbm_step_into(lbm_ctx* ctx, const void* f_src, void* f_dst, int32_t k
     if (!f_src || !f_dst) return fail(&ctx->err, LBM_EINVAL, "f_src and f_dst are required");
     if (f_src == f_dst) return fail(&ctx->err, LBM_EINVAL, "f_src and f_dst must differ (lbm_step updates in place)");
     if (!aligned(f_src) || !aligned(f_dst)) return fail(&ctx->err, LBM_EINVAL, "buffers must be 256-byte aligned");
-    const size_t bytes = size_t(19) * size_t(ctx->g.N) * elem_size(ctx->cfg.storage);
+    const size_t bytes = size_t(ctx->g.lat) * size_t(ctx->g.N) * elem_size(ctx->cfg.storage);
     const char* a0 = static_cast<const char*>(f_src);
     const char* b0 = static_cast<const char*>(f_dst);
     if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(&ctx->err, LBM_EINVAL, "f_src and f_dst overlap");
@@ -720,6 +755,7 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
     ctx->err.clear();
     if (ctx->cfg.storage != LBM_F64 && ctx->cfg.storage != LBM_F32)
         return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for FP64 and FP32 storage only");
+    if (ctx->g.lat != 19) return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for D3Q19 only");
     if (!f_dev || !grad_u_dev || !lambda_dev) return fail(&ctx->err, LBM_EINVAL, "f, grad_u and lambda are required");
     if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
     return device_err(ctx,
@@ -735,6 +771,7 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
     ctx->err.clear();
     if (ctx->cfg.storage != LBM_F64 && ctx->cfg.storage != LBM_F32)
         return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for FP64 and FP32 storage only");
+    if (ctx->g.lat != 19) return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for D3Q19 only");
     if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
     if (!f_t_dev || !lambda_in_dev || !lambda_out_dev)
         return fail(&ctx->err, LBM_EINVAL, "f_t, lambda_in and lambda_out are required");
@@ -779,7 +816,7 @@ lbm_status lbm_probe_pattern(const lbm_config* cfg, void* f_dev, int32_t steps_p
     if (!f_dev || !aligned(f_dev)) return fail(&g_create_err, LBM_EINVAL, "f_dev must be a 256-byte aligned buffer");
     if (steps_per_pass != 1 && steps_per_pass != 2)
         return fail(&g_create_err, LBM_EINVAL, "steps_per_pass must be 1 or 2");
-    if (cfg->storage == LBM_F64 || cfg->nz % 2 != 0 || cfg->variant != 0)
+    if (cfg->storage == LBM_F64 || cfg->nz % 2 != 0 || cfg->variant != 0 || lat_of(*cfg) != 19)
         return fail(&g_create_err, LBM_EUNSUPPORTED,
                     "the pattern probe replicates the pair layout: 32- or 16-bit storage, even nz, variant 0");
     MarchPlan p;
@@ -793,6 +830,7 @@ lbm_status lbm_probe_pattern(const lbm_config* cfg, void* f_dev, int32_t steps_p
     g.nz = cfg->nz;
     g.N = (long long)cfg->nx * cfg->ny * cfg->nz;
     g.PL = (long long)cfg->ny * cfg->nz;
+    g.lat = 19;
     const hipError_t e = launch_probe_pattern(cfg->storage, g, p, f_dev, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess)
         return fail(&g_create_err, LBM_EDEVICE, std::string("pattern probe: ") + hipGetErrorString(e));

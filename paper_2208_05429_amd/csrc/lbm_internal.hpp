@@ -17,6 +17,7 @@ struct Geom {
     int moving_face;  // -1 or 0..5 (-x,+x,-y,+y,-z,+z)
     double uw[3];     // moving-face velocity
     double omega;     // 1/tau
+    int lat;          // velocity set: 19 (D3Q19), 15 (D3Q15) or 27 (D3Q27)
 };
 
 // One in-place marching pass (M = steps merged per pass).

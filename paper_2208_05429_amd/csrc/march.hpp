@@ -37,16 +37,18 @@
 #pragma once
 
 #include "d3q19.hpp"
+#include "lattices.hpp"
 #include "lbm_internal.hpp"
 
 namespace lbm {
 
 // direction masks: bit q set for every q with c_x = +1 / -1
+template <class LT = D3Q19>
 __host__ __device__ constexpr uint32_t mask_cx(int sgn)
 {
     uint32_t m = 0;
-    for (int q = 0; q < Q; ++q)
-        if (cxq(q) == sgn) m |= 1u << q;
+    for (int q = 0; q < LT::Q; ++q)
+        if (LT::cx(q) == sgn) m |= 1u << q;
     return m;
 }
 
@@ -91,16 +93,16 @@ __device__ __forceinline__ void tile_of_item(int item, int nty, int ntz, int& tz
 // come from plane p; afterwards acc[] is the whole plane p-1 (at the level's
 // output time).  bdone: directions of plane p-1 whose source is beyond a wall
 // (their value was deposited earlier).
-template <class R, bool WALLS>
-__device__ __forceinline__ void complete(R (&acc)[Q], const R* __restrict__ X, int stride, int ci, int wz, R o1,
+template <class R, bool WALLS, class LT = D3Q19>
+__device__ __forceinline__ void complete(R (&acc)[LT::Q], const R* __restrict__ X, int stride, int ci, int wz, R o1,
                                          uint32_t bdone)
 {
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        if constexpr (cxq(q) == -1) {
+        if constexpr (LT::cx(q) == -1) {
             R rv;
-            if constexpr (moves_yz(q))
-                rv = X[yz_index(q) * stride + ci - cyq(q) * wz - czq(q)];
+            if constexpr (moves_yz_l<LT>(q))
+                rv = X[yz_index_l<LT>(q) * stride + ci - LT::cy(q) * wz - LT::cz(q)];
             else
                 rv = o1;
             if constexpr (WALLS)
@@ -116,38 +118,38 @@ __device__ __forceinline__ void complete(R (&acc)[Q], const R* __restrict__ X, i
 // one iteration earlier in nxt[]) and put plane p+1's c_x = +1 populations in
 // nxt[].  bnext: directions of plane p whose source is beyond a wall (a
 // moving wall's term was already added at the source, see moving_wall_out).
-template <class R, bool WALLS>
-__device__ __forceinline__ void deposit(R (&acc)[Q], R (&nxt)[5], const R* __restrict__ X, int stride, int ci,
+template <class R, bool WALLS, class LT = D3Q19>
+__device__ __forceinline__ void deposit(R (&acc)[LT::Q], R (&nxt)[nxp<LT>()], const R* __restrict__ X, int stride, int ci,
                                         int wz, R o0, R o1, R o10, uint32_t bnext)
 {
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        constexpr int qo = oppq(q);
+        constexpr int qo = LT::opp(q);
         R bval = R(0);
         if constexpr (WALLS && q != 0) {
-            if constexpr (moves_yz(qo))
-                bval = X[yz_index(qo) * stride + ci];
+            if constexpr (moves_yz_l<LT>(qo))
+                bval = X[yz_index_l<LT>(qo) * stride + ci];
             else
                 bval = (qo == 1) ? o1 : o10;
         }
-        if constexpr (cxq(q) == 0) {
+        if constexpr (LT::cx(q) == 0) {
             R rv;
             if constexpr (q == 0)
                 rv = o0;
             else
-                rv = X[yz_index(q) * stride + ci - cyq(q) * wz - czq(q)];
+                rv = X[yz_index_l<LT>(q) * stride + ci - LT::cy(q) * wz - LT::cz(q)];
             if constexpr (WALLS && q != 0)
                 acc[q] = ((bnext >> q) & 1u) ? bval : rv;
             else
                 acc[q] = rv;
-        } else if constexpr (cxq(q) == 1) {
-            constexpr int j = xp_index(q);
+        } else if constexpr (LT::cx(q) == 1) {
+            constexpr int j = xp_index_l<LT>(q);
             if constexpr (WALLS)
                 acc[q] = ((bnext >> q) & 1u) ? bval : nxt[j];
             else
                 acc[q] = nxt[j];
-            if constexpr (moves_yz(q))
-                nxt[j] = X[yz_index(q) * stride + ci - cyq(q) * wz - czq(q)];
+            if constexpr (moves_yz_l<LT>(q))
+                nxt[j] = X[yz_index_l<LT>(q) * stride + ci - LT::cy(q) * wz - LT::cz(q)];
             else
                 nxt[j] = o10;
         } else {
@@ -156,9 +158,13 @@ __device__ __forceinline__ void deposit(R (&acc)[Q], R (&nxt)[5], const R* __res
     });
 }
 
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
+template <class LT, int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
 __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 {
+    constexpr int QL = LT::Q;                 // velocities
+    constexpr int NYZ = nyz<LT>();            // those that move between columns, exchanged through LDS
+    constexpr int NXP = nxp<LT>();            // those with c_x = +1, carried to the next plane
+    constexpr int XP = LT::H + 1;             // the x-only direction (+1, 0, 0); (-1, 0, 0) is 1
     using Cd = Codec<S>;
     using T = typename Cd::T;
     using R = typename Cd::R;
@@ -169,13 +175,13 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     constexpr int WZ3 = TZ + 2, NC3 = (TY + 2) * WZ3;
     constexpr int K3 = (M == 3) ? K : 1;  // step-3 registers exist for M = 3 only
     constexpr int NB1 = (M == 1) ? 2 : 1;  // a single exchange level is double-buffered
-    constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
+    constexpr uint32_t CXP = mask_cx<LT>(1), CXM = mask_cx<LT>(-1);
     static_assert(M >= 1 && M <= 3, "one to three merged steps");
 
-    __shared__ R X1[NB1][16 * NC];
-    __shared__ R X2[(M >= 2) ? 16 * NC2 : 1];
-    __shared__ R X3[(M == 3) ? 16 * NC3 : 1];
-    __shared__ R WT[WALLS ? Q : 1];  // moving-wall terms (entry q: received along c_q)
+    __shared__ R X1[NB1][NYZ * NC];
+    __shared__ R X2[(M >= 2) ? NYZ * NC2 : 1];
+    __shared__ R X3[(M == 3) ? NYZ * NC3 : 1];
+    __shared__ R WT[WALLS ? QL : 1];  // moving-wall terms (entry q: received along c_q)
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     const bool has_next = !wallx || seg + 1 < a.nseg;
     const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
     const R omega = R(g.omega);
-    if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+    if constexpr (WALLS) wall_terms_to_l<LT>(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
     const long long N = g.N, PL = g.PL;
 
     // ---- columns owned by this thread ----
@@ -244,10 +250,10 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                     if constexpr (M == 3) ci3[k] = (ly - 2) * WZ3 + (lz - 2);
                     if constexpr (WALLS) {
                         uint32_t b = 0, mv = 0;
-                        sfor<1, Q>([&](auto qc) {
+                        sfor<1, QL>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
-                            if constexpr (moves_yz(q)) {
-                                const int ys = y - cyq(q), zs = z - czq(q);
+                            if constexpr (moves_yz_l<LT>(q)) {
+                                const int ys = y - LT::cy(q), zs = z - LT::cz(q);
                                 int f1 = -1, f2 = -1;
                                 if (g.wall[1] && ys < 0) f1 = 2;
                                 if (g.wall[1] && ys >= g.ny) f1 = 3;
@@ -285,20 +291,20 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
 
     // ---- pipeline registers ----
-    T Lr[K][Q];
+    T Lr[K][QL];
     R Fl1[K][3], Fl2[K][3], Fl3[K3][3];
-    R acc1[K][Q], nxt1[K][5], acc2[K][Q], nxt2[K][5], acc3[K3][Q], nxt3[K3][5];
+    R acc1[K][QL], nxt1[K][NXP], acc2[K][QL], nxt2[K][NXP], acc3[K3][QL], nxt3[K3][NXP];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             Lr[k][q] = T(0);
             acc1[k][q] = R(0);
             acc2[k][q] = R(0);
             if constexpr (M == 3) acc3[k][q] = R(0);
         }
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
+        for (int j = 0; j < NXP; ++j) {
             nxt1[k][j] = R(0);
             nxt2[k][j] = R(0);
             if constexpr (M == 3) nxt3[k][j] = R(0);
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         const T* base;
         long long qstride;
         if (from_side) {
-            base = side + ((long long)(nseg_next * M + (xp - e)) * Q) * PL;
+            base = side + ((long long)(nseg_next * M + (xp - e)) * QL) * PL;
             qstride = PL;
         } else {
             base = f + (long long)px * PL;
@@ -341,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         const T* bq = base;  // running pointer: nothing per direction stays live across iterations
         if (!ROUNDS || !(shell_lo || shell_hi) || from_side) {  // (the side planes hold every row at time t)
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
+            for (int q = 0; q < QL; ++q) {
                 Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), loff[k]);
                 bq += qstride;
             }
@@ -363,8 +369,8 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             const uint32_t lofs = (in_lo || in_hi) ? kOffNone : lf;
             const uint32_t olo = in_lo ? lf - lo_first : kOffNone, ohi = in_hi ? lf : kOffNone;
             const uint32_t srange = live ? uint32_t(ss) * uint32_t(sizeof(T)) : 0u;
-            const T* blo = shell_lo ? shell_lo + (long long)px * Q * ss : nullptr;
-            const T* bhi = shell_hi ? shell_hi + (long long)px * Q * ss : nullptr;
+            const T* blo = shell_lo ? shell_lo + (long long)px * QL * ss : nullptr;
+            const T* bhi = shell_hi ? shell_hi + (long long)px * QL * ss : nullptr;
             // Every path issues exactly one load per direction and nothing
             // that reads the loaded values, so the loads stay in flight across
             // the iteration and the compiler's count of outstanding loads is
@@ -376,19 +382,19 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             const bool any_lat = __any(lat), any_lo = __any(in_lo), any_hi = __any(in_hi);
             if (!any_lo && !any_hi) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
+                for (int q = 0; q < QL; ++q) {
                     Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), lf);
                     bq += qstride;
                 }
             } else if (!any_lat && !any_hi) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
+                for (int q = 0; q < QL; ++q) {
                     Lr[k][q] = Buf<T>::ld(make_rsrc(blo, srange), olo);
                     blo += ss;
                 }
             } else if (!any_lat && !any_lo) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
+                for (int q = 0; q < QL; ++q) {
                     Lr[k][q] = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
                     bhi += ss;
                 }
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                 const uintptr_t own = in_lo ? ulo + olo : (in_hi ? uhi + ohi : ula + (lf == kOffNone ? 0u : lf));
                 const uintptr_t step = (in_lo || in_hi) ? dlo : dla;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) Lr[k][q] = *reinterpret_cast<GT*>(own + uintptr_t(q) * step);
+                for (int q = 0; q < QL; ++q) Lr[k][q] = *reinterpret_cast<GT*>(own + uintptr_t(q) * step);
             }
         }
         if constexpr (FORCE) {
@@ -480,11 +486,11 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     // Stores, like loads, are issued every iteration by every slot; lanes that
     // do not own a finished interior column carry an out-of-range offset and a
     // plane that is not stored this iteration gets an empty range.
-    auto store = [&](const R (&out)[Q], int k, int r, bool live) {
+    auto store = [&](const R (&out)[QL], int k, int r, bool live) {
         const T* bq = fo + (long long)(live ? r : 0) * PL;
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             Buf<T>::st(Cd::enc(out[q]), make_rsrc(bq, range), soff[k]);
             bq += N;
         }
@@ -538,19 +544,19 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                 for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
             }
             if (pres && rad[k] <= M && gofs[k] >= 0) {
-                R v[Q];
+                R v[QL];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lr[k][q]);
-                collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+                for (int q = 0; q < QL; ++q) v[q] = Cd::dec(Lr[k][q]);
+                LT::template collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
                 const int c = tid + k * NT;
-                sfor<0, Q>([&](auto qc) {
+                sfor<0, QL>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
-                    if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + c] = v[q];
+                    if constexpr (moves_yz_l<LT>(q)) X1w[yz_index_l<LT>(q) * NC + c] = v[q];
                 });
-                if constexpr (WALLS) moving_wall_out(v[1], v[10], X1w, NC, c, myz[k] | xmc, WT);
+                if constexpr (WALLS) moving_wall_out_l<LT>(v[1], v[XP], X1w, NC, c, myz[k] | xmc, WT);
                 o1[k][0] = v[0];
                 o1[k][1] = v[1];
-                o1[k][2] = v[10];
+                o1[k][2] = v[XP];
             }
             issue_load_slot(xl + 1, next_wanted, k);
         }
@@ -564,23 +570,23 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             for (int k = 0; k < K; ++k) {
                 const bool act = rad[k] == 0 && gofs[k] >= 0;
                 if constexpr (M == 3) {
-                    if (act) complete<R, WALLS>(acc3[k], X3, NC3, ci3[k], WZ3, o3[k][1], byz[k] | xbd);
+                    if (act) complete<R, WALLS, LT>(acc3[k], X3, NC3, ci3[k], WZ3, o3[k][1], byz[k] | xbd);
                     store(acc3[k], k, r_out, storing);
                     if (act)
-                        deposit<R, WALLS>(acc3[k], nxt3[k], X3, NC3, ci3[k], WZ3, o3[k][0], o3[k][1], o3[k][2],
+                        deposit<R, WALLS, LT>(acc3[k], nxt3[k], X3, NC3, ci3[k], WZ3, o3[k][0], o3[k][1], o3[k][2],
                                           byz[k] | xbn);
                 } else if constexpr (M == 2) {
-                    if (act) complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
+                    if (act) complete<R, WALLS, LT>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
                     store(acc2[k], k, r_out, storing);
                     if (act)
-                        deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
+                        deposit<R, WALLS, LT>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
                                           byz[k] | xbn);
                 } else {
                     const int c = tid + k * NT;
-                    if (act) complete<R, WALLS>(acc1[k], X1r, NC, c, WZ, o1p[k][1], byz[k] | xbd);
+                    if (act) complete<R, WALLS, LT>(acc1[k], X1r, NC, c, WZ, o1p[k][1], byz[k] | xbd);
                     store(acc1[k], k, r_out, storing);
                     if (act)
-                        deposit<R, WALLS>(acc1[k], nxt1[k], X1r, NC, c, WZ, o1p[k][0], o1p[k][1], o1p[k][2],
+                        deposit<R, WALLS, LT>(acc1[k], nxt1[k], X1r, NC, c, WZ, o1p[k][0], o1p[k][1], o1p[k][2],
                                           byz[k] | xbn);
                 }
             }
@@ -604,20 +610,20 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             for (int k = 0; k < K; ++k) {
                 if (rad[k] <= M - 1 && gofs[k] >= 0) {
                     const int c = tid + k * NT;
-                    complete<R, WALLS>(acc1[k], X1w, NC, c, WZ, o1[k][1], byz[k] | xbd1);
+                    complete<R, WALLS, LT>(acc1[k], X1w, NC, c, WZ, o1[k][1], byz[k] | xbd1);
                     if (coll2) {
-                        collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
-                        sfor<0, Q>([&](auto qc) {
+                        LT::template collide<R, FORCE>(acc1[k], omega, Fl2[k][0], Fl2[k][1], Fl2[k][2]);
+                        sfor<0, QL>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
-                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + ci2[k]] = acc1[k][q];
+                            if constexpr (moves_yz_l<LT>(q)) X2[yz_index_l<LT>(q) * NC2 + ci2[k]] = acc1[k][q];
                         });
                         if constexpr (WALLS)
-                            moving_wall_out(acc1[k][1], acc1[k][10], X2, NC2, ci2[k], myz[k] | xmc2, WT);
+                            moving_wall_out_l<LT>(acc1[k][1], acc1[k][XP], X2, NC2, ci2[k], myz[k] | xmc2, WT);
                         o2[k][0] = acc1[k][0];
                         o2[k][1] = acc1[k][1];
-                        o2[k][2] = acc1[k][10];
+                        o2[k][2] = acc1[k][XP];
                     }
-                    deposit<R, WALLS>(acc1[k], nxt1[k], X1w, NC, c, WZ, o1[k][0], o1[k][1], o1[k][2],
+                    deposit<R, WALLS, LT>(acc1[k], nxt1[k], X1w, NC, c, WZ, o1[k][0], o1[k][1], o1[k][2],
                                       byz[k] | xbn1);
                 }
                 if constexpr (FORCE && M == 2) {
@@ -636,20 +642,20 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (rad[k] <= M - 2 && gofs[k] >= 0) {
-                    complete<R, WALLS>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd2);
+                    complete<R, WALLS, LT>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd2);
                     if (coll3) {
-                        collide<R, FORCE>(acc2[k], omega, Fl3[k][0], Fl3[k][1], Fl3[k][2]);
-                        sfor<0, Q>([&](auto qc) {
+                        LT::template collide<R, FORCE>(acc2[k], omega, Fl3[k][0], Fl3[k][1], Fl3[k][2]);
+                        sfor<0, QL>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
-                            if constexpr (moves_yz(q)) X3[yz_index(q) * NC3 + ci3[k]] = acc2[k][q];
+                            if constexpr (moves_yz_l<LT>(q)) X3[yz_index_l<LT>(q) * NC3 + ci3[k]] = acc2[k][q];
                         });
                         if constexpr (WALLS)
-                            moving_wall_out(acc2[k][1], acc2[k][10], X3, NC3, ci3[k], myz[k] | xmc3, WT);
+                            moving_wall_out_l<LT>(acc2[k][1], acc2[k][XP], X3, NC3, ci3[k], myz[k] | xmc3, WT);
                         o3[k][0] = acc2[k][0];
                         o3[k][1] = acc2[k][1];
-                        o3[k][2] = acc2[k][10];
+                        o3[k][2] = acc2[k][XP];
                     }
-                    deposit<R, WALLS>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
+                    deposit<R, WALLS, LT>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
                                       byz[k] | xbn2);
                 }
                 if constexpr (FORCE) {
@@ -669,22 +675,22 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
 // Launch of one compiled shape.  Cooperative launch guarantees co-residency
 // of all work items (required by the progress-counter protocol).
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, class LT = D3Q19>
 hipError_t launch_march_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
 {
-    auto kern = k_march<S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>;
+    auto kern = k_march<LT, S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>;
     MarchArgs arg = a;
     void* params[] = {&arg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks), dim3(NT), params, 0, st);
 }
 
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, class LT = D3Q19>
 int max_blocks_shape()
 {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>, NT,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<LT, S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>, NT,
                                                      0) != hipSuccess)
         return 0;
     return per_cu * cus;

@@ -317,6 +317,7 @@ lbm_status setup(const lbm_config* cfg, double* g, Lat* L)
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return LBM_EINVAL;
     if (!(cfg->tau > 0.5) || !isfinite(cfg->tau)) return LBM_EINVAL;
     if (cfg->use_force) return LBM_EUNSUPPORTED;
+    if (cfg->velocities != 0 && cfg->velocities != 19) return LBM_EUNSUPPORTED;  // D3Q19, as the paper
     int moving = -1;
     for (int a = 0; a < 3; ++a) {
         const int lo = cfg->face[2 * a], hi = cfg->face[2 * a + 1];

@@ -35,23 +35,26 @@ class Lattice:
     faces    6 codes for -x,+x,-y,+y,-z,+z ('periodic' | 'wall' | 'moving')
     force    optional torch tensor (3, nx, ny, nz) of real_dtype(storage)
     rho0/u0  optional float64 tensors (nx,ny,nz) / (3,nx,ny,nz); None = 1 / 0
+    velocities  19 (D3Q19), 15 or 27 (the other cubic sets; FP64/FP32 storage)
     """
 
     def __init__(self, shape, tau, storage="f32", scheme="swap2", faces=("periodic",) * 6,
-                 wall_u=(0.0, 0.0, 0.0), force=None, rho0=None, u0=None, variant=0, device=None, f=None):
+                 wall_u=(0.0, 0.0, 0.0), force=None, rho0=None, u0=None, variant=0, device=None, f=None,
+                 velocities=19):
         self.shape = tuple(int(s) for s in shape)
         self.N = int(np.prod(self.shape))
         self.storage, self.scheme = storage, scheme
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         fcodes = [FACE[f] if isinstance(f, str) else int(f) for f in faces]
+        self.Q = int(velocities)
         self.cfg = capi.make_config(self.shape, tau, STORAGE[storage], SCHEME[scheme], fcodes, wall_u,
-                                    force is not None, variant)
+                                    force is not None, variant, self.Q)
         fb, wb = capi.lbm_buffer_sizes(self.cfg)
         dt = _STORE_DTYPE[storage]
         if f is None:
-            self.f = torch.empty((19,) + self.shape, dtype=dt, device=self.device)
+            self.f = torch.empty((self.Q,) + self.shape, dtype=dt, device=self.device)
         else:
-            assert f.dtype == dt and f.is_contiguous() and tuple(f.shape) == (19,) + self.shape
+            assert f.dtype == dt and f.is_contiguous() and tuple(f.shape) == (self.Q,) + self.shape
             self.f = f
         assert self.f.numel() * self.f.element_size() == fb
         self.work = torch.empty(max(wb, 256), dtype=torch.uint8, device=self.device)
@@ -108,18 +111,21 @@ class Lattice:
     def distributions(self):
         """f = g + w as float64 (host numpy), layout [q, x, y, z]."""
         g = self.f.to(torch.float64).cpu().numpy()
-        return g + lattice_weights()[:, None, None, None]
+        return g + lattice_weights(self.Q)[:, None, None, None]
 
 
-def lattice_weights():
-    """D3Q19 weights in the library's direction order (1/3, six 1/18, twelve 1/36)."""
-    c = lattice_velocities()
-    c2 = (c ** 2).sum(axis=1)
-    return np.where(c2 == 0, 1 / 3, np.where(c2 == 1, 1 / 18, 1 / 36))
+def lattice_weights(q=19):
+    """Weights of velocity set D3Q{q} in the library's direction order."""
+    c2 = (lattice_velocities(q) ** 2).sum(axis=1)
+    by_speed = {15: (2 / 9, 1 / 9, 0.0, 1 / 72), 19: (1 / 3, 1 / 18, 1 / 36, 0.0),
+                27: (8 / 27, 2 / 27, 1 / 54, 1 / 216)}[q]
+    return np.array([by_speed[s] for s in c2])
 
 
-def lattice_velocities():
+def lattice_velocities(q=19):
     """The direction order of include/lbm.h (interface, not arithmetic)."""
     half = [(-1, 0, 0), (0, -1, 0), (0, 0, -1), (-1, -1, 0), (-1, 1, 0), (-1, 0, -1), (-1, 0, 1), (0, -1, -1),
             (0, -1, 1)]
+    corners = [(-1, -1, -1), (-1, -1, 1), (-1, 1, -1), (-1, 1, 1)]
+    half = {19: half, 15: half[:3] + corners, 27: half + corners}[q]
     return np.array([(0, 0, 0)] + half + [tuple(-v for v in h) for h in half], dtype=np.int64)

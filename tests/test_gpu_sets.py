@@ -1,0 +1,121 @@
+"""D3Q15 and D3Q27 (lbm_config.velocities; Sec. 4.1 names both as velocity
+sets the two-step rule holds for) through the C ABI against the FP64 oracle
+of the same set (oracle/lbm_oracle_q.c, pinned on the CPU): every scheme,
+FP64 within 1e-12 and FP32 within 2e-6 of the oracle per field, and the
+in-place single-copy schemes equal to the two-array kernel to the bit (the
+same per-cell arithmetic).  Ragged tiles, walls, a moving lid, a body force,
+odd step counts; FP32 over 100 steps on the 32^3 Taylor-Green vortex."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import MOVING_WALL, PERIODIC, WALL, OracleQ
+from paper_2208_05429_amd import capi
+from paper_2208_05429_amd import workloads as wl
+from paper_2208_05429_amd.lattice import Lattice, real_dtype
+
+pytestmark = pytest.mark.gpu
+
+NAMES = {PERIODIC: "periodic", WALL: "wall", MOVING_WALL: "moving"}
+CASES = [
+    ((20, 37, 45), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, -0.02)),
+    ((23, 30, 61), (PERIODIC, PERIODIC, WALL, WALL, MOVING_WALL, WALL), (0.03, -0.02, 0.0)),
+    ((17, 41, 33), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((26, 13, 70), (MOVING_WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.04, 0.01)),
+    ((6, 5, 7), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),  # one tile smaller than the halo frame
+]
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _init(shape, seed):
+    _, u0 = wl.taylor_green_3d(shape, 0.03)
+    return wl.random_density(shape, 0.01, seed + 1), u0 + wl.uniform_noise(shape, 5e-3, seed)
+
+
+def _run(q, shape, tau, storage, scheme, faces, wall_u, rho0, u0, steps, F=None):
+    print(f"[gpu] D3Q{q} {storage} {scheme} {shape} {steps} steps faces={faces}", flush=True)
+    force = None if F is None else torch.as_tensor(F, dtype=real_dtype(storage))
+    lat = Lattice(shape, tau, storage, scheme, [NAMES[f] for f in faces], wall_u, force, torch.as_tensor(rho0),
+                  torch.as_tensor(u0), velocities=q)
+    lat.step(steps)
+    rho, u, un, sums = lat.macroscopic(sums=True)
+    torch.cuda.synchronize()
+    out = (lat.distributions(), rho.cpu().numpy(), u.cpu().numpy(), un.cpu().numpy(), sums, lat.f.clone())
+    lat.close()
+    return out
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_sets_match_the_oracle_and_schemes_agree(q, storage, tol, case):
+    shape, faces, wall_u = CASES[case]
+    rho0, u0 = _init(shape, 600 + case)
+    steps = 9
+    o = OracleQ(shape, 0.7, q, faces=faces, wall_u=wall_u)
+    ref = o.run(o.init(rho0, u0), steps)
+    r_ref, u_ref, un_ref = o.macro(ref)
+    s_ref = o.sums(ref)
+    base = None
+    for scheme in ("two_array", "swap1", "swap2"):
+        f, rho, u, un, sums, raw = _run(q, shape, 0.7, storage, scheme, faces, wall_u, rho0, u0, steps)
+        assert rel(f, ref) <= tol and rel(rho, r_ref) <= tol and rel(u, u_ref) <= tol and rel(un, un_ref) <= tol
+        assert abs(sums[0] - s_ref[0]) <= 1e-12 * s_ref[0] * (1 if storage == "f64" else 1e4)
+        view = torch.int64 if storage == "f64" else torch.int32
+        if base is None:
+            base = raw.view(view)
+        else:
+            assert torch.equal(raw.view(view), base), scheme
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_sets_with_a_body_force(q):
+    shape = (24, 20, 18)
+    faces = (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL)
+    rho0, u0 = _init(shape, 700)
+    F = wl.normal_field(shape, 1e-4, 701)
+    o = OracleQ(shape, 0.8, q, faces=faces)
+    ref = o.run(o.init(rho0, u0), 7, F)
+    _, u_ref, _ = o.macro(ref, F)
+    for storage, tol in (("f64", 1e-12), ("f32", 2e-6)):
+        base = None
+        for scheme in ("two_array", "swap2"):
+            f, _, u, _, _, raw = _run(q, shape, 0.8, storage, scheme, faces, (0, 0, 0), rho0, u0, 7, F)
+            assert rel(f, ref) <= tol
+            view = torch.int64 if storage == "f64" else torch.int32
+            if base is None:
+                base = raw.view(view)
+            else:
+                assert torch.equal(raw.view(view), base), (storage, scheme)
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_sets_fp32_taylor_green_100_steps(q):
+    cfg = wl.TGV_32
+    rho0, u0 = wl.taylor_green_3d(cfg["shape"], cfg["u0"])
+    o = OracleQ(cfg["shape"], cfg["tau"], q)
+    ref = o.run(o.init(rho0, u0), cfg["steps"])
+    r_ref, u_ref, un_ref = o.macro(ref)
+    for scheme in ("two_array", "swap2"):
+        _, rho, u, un, _, _ = _run(q, cfg["shape"], cfg["tau"], "f32", scheme, (PERIODIC,) * 6, (0, 0, 0), rho0, u0,
+                                   cfg["steps"])
+        e = (rel(rho, r_ref), rel(u, u_ref), rel(un, un_ref))
+        print(f"D3Q{q} FP32 {scheme} TGV 32^3 100 steps: rho {e[0]:.2e} u {e[1]:.2e} |u| {e[2]:.2e}")
+        assert max(e) <= 2e-6
+
+
+def test_sets_run_without_allocation_too():
+    # the allocation-free entry point takes the same configurations
+    shape = (20, 24, 30)
+    rho0, u0 = _init(shape, 710)
+    lat = Lattice(shape, 0.7, "f32", "swap2", ["wall"] * 3 + ["moving"] + ["wall"] * 2, (0.04, 0, 0),
+                  rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0), velocities=27)
+    f2 = lat.f.clone()
+    lat.step(5)
+    capi.lbm_step_static(lat.cfg, f2.data_ptr(), None, 5, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(lat.f.view(torch.int32), f2.view(torch.int32))
+    lat.close()

@@ -160,7 +160,7 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def adjoint_ratio(shape, steps, checkpoint, reps=3):
+def adjoint_ratio(shape, steps, checkpoint, reps=3, scheme="swap2", merged=True):
     """Backward (recompute + merged adjoint) time per step over merged forward
     time per step, for L = sum |u_T - u*|^2 on a channel (periodic x, walls in
     y and z, tau 0.8) under a per-cell force N(0, 1e-12) (seed 1); u* from a
@@ -179,8 +179,9 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
     lat.step(steps)
     _, ut, _, _ = lat.macroscopic(want=("u",))
     lat.close()
-    lat = Lattice(shape, 0.8, "f32", "swap2", faces, force=F, f=f0.clone())
-    spec = dict(shape=shape, tau=0.8, storage="f32", faces=faces, steps=steps, checkpoint=checkpoint, merged=True)
+    lat = Lattice(shape, 0.8, "f32", scheme, faces, force=F, f=f0.clone())
+    spec = dict(shape=shape, tau=0.8, storage="f32", faces=faces, steps=steps, checkpoint=checkpoint, merged=merged,
+                scheme=scheme)
     fwd, bwd, ckf = [], [], []
     for r in range(reps + 1):
         lat.f.copy_(f0)
@@ -206,7 +207,9 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
             fwd.append(e0.elapsed_time(e1))
             bwd.append(b0.elapsed_time(b1))
             ckf.append(c0.elapsed_time(c1))
-    # the adjoint kernel alone, one merged reverse pass, against one merged forward pass
+    # the adjoint kernel alone (one reverse call of the configuration's steps)
+    # against the forward kernel over the same steps (out of place)
+    kk = 2 if merged else 1
     lam = torch.randn((19,) + tuple(shape), device="cuda")
     lout = torch.empty_like(lam)
     gF = torch.zeros((3,) + tuple(shape), device="cuda")
@@ -215,19 +218,20 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3):
     a0, a1 = _events()
     a0.record()
     for _ in range(n):
-        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lam.data_ptr(), lout.data_ptr(), gF.data_ptr(), 2)
+        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lam.data_ptr(), lout.data_ptr(), gF.data_ptr(), kk)
     a1.record()
     f1 = torch.empty_like(lat.f)
     m0, m1 = _events()
     m0.record()
     for _ in range(n):
-        lat.step_into(lat.f, f1, 2)
+        lat.step_into(lat.f, f1, kk)
     m1.record()
     torch.cuda.synchronize()
     lat.close()
     fw, bw, cf = float(np.median(fwd)) / steps, float(np.median(bwd)) / steps, float(np.median(ckf)) / steps
-    ka, kf = a0.elapsed_time(a1) / (2 * n), m0.elapsed_time(m1) / (2 * n)
-    return {"shape": list(shape), "steps": steps, "checkpoint": checkpoint, "forward_ms_per_step": round(fw, 5),
+    ka, kf = a0.elapsed_time(a1) / (kk * n), m0.elapsed_time(m1) / (kk * n)
+    return {"shape": list(shape), "steps": steps, "checkpoint": checkpoint, "scheme": scheme,
+            "reverse_steps_per_call": 2 if merged else 1, "forward_ms_per_step": round(fw, 5),
             "backward_ms_per_step": round(bw, 5), "ratio": round(bw / fw, 3),
             "checkpointing_forward_ms_per_step": round(cf, 5),
             "adjoint_kernel_ms_per_step": round(ka, 5), "forward_kernel_ms_per_step": round(kf, 5),
@@ -473,7 +477,7 @@ def main():
                                                              stream.cuda_stream)), 1)
                for b in (256, 1024, 4096)}
         torch_gbs = best_of(lambda: dst.copy_(src))
-        copy_gbs = max(hip.values())
+        copy_gbs = round(max(max(hip.values()), torch_gbs), 1)  # the best copy measured
         out["roofline"]["copy_gbs"] = copy_gbs
         out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
         out["copy_probe"] = {"bytes": a.copy_probe, "hip_copy16_gbs_by_grid": hip,
@@ -495,7 +499,15 @@ def main():
         out["large_1024_f64"] = large_run(1024, 10, "f64")
     if not a.no_adjoint:
         print("[bench] adjoint/forward ratio", file=sys.stderr, flush=True)
-        out["adjoint"] = {"workload": adjoint_ratio((128, 64, 64), 200, 20),
+        wk = adjoint_ratio((128, 64, 64), 200, 20)
+        # on this small lattice the marching passes are bound by the latency
+        # of each plane: the plain two-array scheme (forward and recompute)
+        # with single reverse steps is the faster configuration
+        wk2 = adjoint_ratio((128, 64, 64), 200, 20, scheme="two_array", merged=False)
+        best_fw = min(wk["forward_ms_per_step"], wk2["forward_ms_per_step"])
+        best_bw = min(wk["backward_ms_per_step"], wk2["backward_ms_per_step"])
+        out["adjoint"] = {"workload": wk, "workload_two_array_single_reverse_steps": wk2,
+                          "workload_best_backward_over_best_forward": round(best_bw / best_fw, 3),
                           "bandwidth_bound": adjoint_ratio((256, 256, 256), 40, 20, reps=2),
                           # every other state kept (20 x 1.3 GB): no recompute in the backward
                           "bandwidth_bound_every_other_state": adjoint_ratio((256, 256, 256), 40, 2, reps=2)}

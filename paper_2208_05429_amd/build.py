@@ -32,7 +32,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
 
 
 # the sources the marching kernels and their launch are built from
-MARCH_SOURCES = ("d3q19.hpp", "lbm_internal.hpp", "march.hpp", "march_pr.hpp", "march_dispatch.hpp",
+MARCH_SOURCES = ("d3q19.hpp", "lattices.hpp", "lbm_internal.hpp", "march.hpp", "march_pr.hpp", "march_dispatch.hpp",
                  "march_f32.hip", "march_f16.hip", "march_bf16.hip", "march_f64.hip", "lbm_api.cpp", "k_basic.hip")
 
 

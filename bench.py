@@ -520,6 +520,11 @@ def main():
         print("[bench] the paper's CPU algorithms on the host", file=sys.stderr, flush=True)
         out["cpu_context"] = cpu_context()
     print(json.dumps(out), flush=True)
+    # every library context is released before the interpreter exits (those
+    # the autograd graphs held go with the graphs)
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

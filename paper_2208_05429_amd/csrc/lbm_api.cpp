@@ -72,10 +72,10 @@ lbm_status fail(std::string* where, lbm_status st, const std::string& msg)
 bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPlan* r, int lat = 19)
 {
     if (lat != 19) {
-        // D3Q15 / D3Q27: one shape per storage and step count
-        if (variant != 0 || M > 2) return false;
+        // D3Q15 / D3Q27: shapes by storage, variant and step count
+        if (M > 2) return false;
         for (const SetShapes& e : kSetShapes)
-            if (e.lat == lat && e.storage == storage) {
+            if (e.lat == lat && e.storage == storage && e.variant == variant) {
                 const ShapeEntry& t = M == 2 ? e.m2 : e.m1;
                 r->TY = t.TY;
                 r->TZ = t.TZ;

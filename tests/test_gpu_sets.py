@@ -119,3 +119,27 @@ def test_sets_run_without_allocation_too():
     torch.cuda.synchronize()
     assert torch.equal(lat.f.view(torch.int32), f2.view(torch.int32))
     lat.close()
+
+
+@pytest.mark.parametrize("q,variant", [(15, 1), (15, 2), (27, 1)])
+@pytest.mark.parametrize("case", [0, 1, 2])
+def test_set_tile_variants_equal_two_array_bitwise(q, variant, case):
+    # the larger FP32 tiles (two or three columns per thread)
+    shape, faces, wall_u = CASES[case]
+    rho0, u0 = _init(shape, 720 + case)
+    names = [NAMES[f] for f in faces]
+    ref = Lattice(shape, 0.7, "f32", "two_array", names, wall_u, None, torch.as_tensor(rho0), torch.as_tensor(u0),
+                  velocities=q)
+    print(f"[gpu] D3Q{q} variant {variant} {shape}", flush=True)
+    for scheme in ("swap2", "swap1"):
+        lat = Lattice(shape, 0.7, "f32", scheme, names, wall_u, None, torch.as_tensor(rho0), torch.as_tensor(u0),
+                      variant=variant, velocities=q)
+        lat.f.copy_(ref.f)
+        r = Lattice(shape, 0.7, "f32", "two_array", names, wall_u, f=ref.f.clone(), velocities=q)
+        lat.step(5)
+        r.step(5)
+        torch.cuda.synchronize()
+        assert torch.equal(lat.f.view(torch.int32), r.f.view(torch.int32)), (scheme, variant)
+        lat.close()
+        r.close()
+    ref.close()

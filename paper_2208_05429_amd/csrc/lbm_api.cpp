@@ -14,6 +14,7 @@
 #include "../../include/lbm.h"
 #include "lbm_internal.hpp"
 #include "march_dispatch.hpp"
+#include "march_sets.hpp"
 
 using namespace lbm;
 

@@ -1,7 +1,7 @@
 // march_sets.hip -- marching-kernel instantiations for the D3Q15 and D3Q27
 // velocity sets: the one-column-per-thread layout of march.hpp, FP64 and
 // FP32 storage, one and two merged steps, one round per pass.
-#include "march_dispatch.hpp"
+#include "march_sets.hpp"
 
 namespace lbm {
 
@@ -29,7 +29,7 @@ struct SetShape {
     }
 };
 
-// the shapes of kSetShapes (march_dispatch.hpp), in the same order
+// the shapes of kSetShapes (march_sets.hpp)
 using List_q15_f32 = ShapeList<SetShape<D3Q15, ST_F32, 2, 12, 28, 512>, SetShape<D3Q15, ST_F32, 1, 14, 30, 512>,
                                SetShape<D3Q15, ST_F32, 2, 16, 32, 512>, SetShape<D3Q15, ST_F32, 1, 16, 32, 512>,
                                SetShape<D3Q15, ST_F32, 2, 16, 64, 512>, SetShape<D3Q15, ST_F32, 1, 16, 64, 512>>;

@@ -81,8 +81,20 @@ bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPl
                 r->TY = t.TY;
                 r->TZ = t.TZ;
                 r->NT = t.NT;
-                r->pr = 0;
+                r->pr = t.pr;
                 r->pf = 1;
+                if (t.pr && ((nz % 2) != 0 || plain)) {
+                    // pairs need an even row: the plain layout of the same tile
+                    for (const SetShapes& o : kSetShapes) {
+                        const ShapeEntry& u = M == 2 ? o.m2 : o.m1;
+                        if (o.lat == lat && o.storage == storage && !u.pr && u.TY == t.TY && u.TZ == t.TZ) {
+                            r->NT = u.NT;
+                            r->pr = 0;
+                            return true;
+                        }
+                    }
+                    return false;
+                }
                 return true;
             }
         return false;

@@ -125,18 +125,18 @@ __device__ __forceinline__ int opaque(int v)
     return v;
 }
 
-template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
-__device__ __forceinline__ void complete_s(R (&acc)[Q], const R* __restrict__ X, int ci, R o1, uint32_t xw)
+template <class R, bool WALLS, int PAR, int STRIDE, int WZL, class LT = D3Q19>
+__device__ __forceinline__ void complete_s(R (&acc)[LT::Q], const R* __restrict__ X, int ci, R o1, uint32_t xw)
 {
     constexpr int HALF = STRIDE / 2;
     // next to an x wall (uniform over the plane) every c_x = -1 population was
     // put in place by deposit_s, and there is nothing to receive
-    if (WALLS && (xw & mask_cx(-1)) != 0u) return;
-    sfor<0, Q>([&](auto qc) {
+    if (WALLS && (xw & mask_cx<LT>(-1)) != 0u) return;
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        if constexpr (cxq(q) == -1) {
-            if constexpr (moves_yz(q))
-                acc[q] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
+        if constexpr (LT::cx(q) == -1) {
+            if constexpr (moves_yz_l<LT>(q))
+                acc[q] = X[yz_index_l<LT>(q) * STRIDE + split_at<PAR, HALF>(ci, -LT::cy(q) * WZL - LT::cz(q))];
             else
                 acc[q] = o1;
         }
@@ -144,33 +144,33 @@ __device__ __forceinline__ void complete_s(R (&acc)[Q], const R* __restrict__ X,
 }
 
 // own reversed post-collision value of direction q (its opposite's slot)
-template <class R, int PAR, int STRIDE, int q>
+template <class R, int PAR, int STRIDE, int q, class LT = D3Q19>
 __device__ __forceinline__ R own_reversed(const R* __restrict__ X, int ci, R o1, R o10)
 {
-    constexpr int qo = oppq(q);
-    if constexpr (moves_yz(qo))
-        return X[yz_index(qo) * STRIDE + split_at<PAR, STRIDE / 2>(ci, 0)];
+    constexpr int qo = LT::opp(q);
+    if constexpr (moves_yz_l<LT>(qo))
+        return X[yz_index_l<LT>(qo) * STRIDE + split_at<PAR, STRIDE / 2>(ci, 0)];
     else
         return (qo == 1) ? o1 : o10;
 }
 
-template <class R, bool WALLS, int PAR, int STRIDE, int WZL>
-__device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], R* __restrict__ X, int ci, R o0, R o1, R o10,
+template <class R, bool WALLS, int PAR, int STRIDE, int WZL, class LT = D3Q19>
+__device__ __forceinline__ void deposit_s(R (&acc)[LT::Q], R (&nxt)[nxp<LT>()], R* __restrict__ X, int ci, R o0, R o1, R o10,
                                           uint32_t xw, uint32_t byz, uint32_t mv, const R* WT, R* Xg, int lane)
 {
     constexpr int HALF = STRIDE / 2;
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        if constexpr (cxq(q) == 0) {
+        if constexpr (LT::cx(q) == 0) {
             if constexpr (q == 0)
                 acc[q] = o0;
             else
-                acc[q] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
-        } else if constexpr (cxq(q) == 1) {
-            constexpr int j = xp_index(q);
+                acc[q] = X[yz_index_l<LT>(q) * STRIDE + split_at<PAR, HALF>(ci, -LT::cy(q) * WZL - LT::cz(q))];
+        } else if constexpr (LT::cx(q) == 1) {
+            constexpr int j = xp_index_l<LT>(q);
             acc[q] = nxt[j];
-            if constexpr (moves_yz(q))
-                nxt[j] = X[yz_index(q) * STRIDE + split_at<PAR, HALF>(ci, -cyq(q) * WZL - czq(q))];
+            if constexpr (moves_yz_l<LT>(q))
+                nxt[j] = X[yz_index_l<LT>(q) * STRIDE + split_at<PAR, HALF>(ci, -LT::cy(q) * WZL - LT::cz(q))];
             else
                 nxt[j] = o10;
         }
@@ -178,24 +178,24 @@ __device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], R* __restric
     if constexpr (WALLS) {
         if (xw != 0u) {  // a plane next to an x wall (uniform)
             const int cio = opaque(ci);
-            sfor<1, Q>([&](auto qc) {
+            sfor<1, LT::Q>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                if constexpr (cxq(q) != 0) {
+                if constexpr (LT::cx(q) != 0) {
                     if ((xw >> q) & 1u) {
-                        const R own = own_reversed<R, PAR, STRIDE, q>(X, cio, o1, o10);
+                        const R own = own_reversed<R, PAR, STRIDE, q, LT>(X, cio, o1, o10);
                         acc[q] = ((mv >> q) & 1u) ? own + WT[opaque(q)] : own;
                     }
                 }
             });
         }
         if (__any(byz != 0u)) {  // c_x = -1 ghosts for the next plane's completion
-            const int cio = opaque(ci), sk = opaque(16 * STRIDE + lane);
-            sfor<1, Q>([&](auto qc) {
+            const int cio = opaque(ci), sk = opaque(nyz<LT>() * STRIDE + lane);
+            sfor<1, LT::Q>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                if constexpr (cxq(q) == -1 && moves_yz(q)) {
+                if constexpr (LT::cx(q) == -1 && moves_yz_l<LT>(q)) {
                     const bool hit = (byz >> q) & 1u;
-                    const R own = own_reversed<R, PAR, STRIDE, q>(X, cio, o1, o10);
-                    const int gi = yz_index(q) * STRIDE + split_at<PAR, HALF>(cio, -cyq(q) * WZL - czq(q));
+                    const R own = own_reversed<R, PAR, STRIDE, q, LT>(X, cio, o1, o10);
+                    const int gi = yz_index_l<LT>(q) * STRIDE + split_at<PAR, HALF>(cio, -LT::cy(q) * WZL - LT::cz(q));
                     Xg[hit ? gi : sk] = ((mv >> q) & 1u) ? own + WT[opaque(q)] : own;
                 }
             });
@@ -205,23 +205,23 @@ __device__ __forceinline__ void deposit_s(R (&acc)[Q], R (&nxt)[5], R* __restric
 
 // Right after a receiving cell's collision (v: its post-collision values,
 // already written to its own slots): c_x = 0 ghosts and c_x = +1 replacements.
-template <class R, int PAR, int STRIDE, int WZL>
-__device__ __forceinline__ void ghost_out(const R (&v)[Q], R (&nxt)[5], R* __restrict__ X, int ci, uint32_t byz,
+template <class R, int PAR, int STRIDE, int WZL, class LT = D3Q19>
+__device__ __forceinline__ void ghost_out(const R (&v)[LT::Q], R (&nxt)[nxp<LT>()], R* __restrict__ X, int ci, uint32_t byz,
                                           uint32_t myz, const R* WT, int lane)
 {
     constexpr int HALF = STRIDE / 2;
     if (!__any(byz != 0u)) return;
-    const int cio = opaque(ci), sk = opaque(16 * STRIDE + lane);
-    sfor<1, Q>([&](auto qc) {
+    const int cio = opaque(ci), sk = opaque(nyz<LT>() * STRIDE + lane);
+    sfor<1, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        if constexpr (moves_yz(q) && cxq(q) >= 0) {
+        if constexpr (moves_yz_l<LT>(q) && LT::cx(q) >= 0) {
             const bool hit = (byz >> q) & 1u;
-            const R val = ((myz >> q) & 1u) ? v[oppq(q)] + WT[opaque(q)] : v[oppq(q)];
-            if constexpr (cxq(q) == 0) {
-                const int gi = yz_index(q) * STRIDE + split_at<PAR, HALF>(cio, -cyq(q) * WZL - czq(q));
+            const R val = ((myz >> q) & 1u) ? v[LT::opp(q)] + WT[opaque(q)] : v[LT::opp(q)];
+            if constexpr (LT::cx(q) == 0) {
+                const int gi = yz_index_l<LT>(q) * STRIDE + split_at<PAR, HALF>(cio, -LT::cy(q) * WZL - LT::cz(q));
                 X[hit ? gi : sk] = val;
             } else {
-                nxt[xp_index(q)] = hit ? val : nxt[xp_index(q)];
+                nxt[xp_index_l<LT>(q)] = hit ? val : nxt[xp_index_l<LT>(q)];
             }
         }
     });
@@ -274,24 +274,28 @@ __device__ __forceinline__ bool ring_cell(int r, bool banded, int& ly, int& lz)
     return false;
 }
 
-template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF, class LT = D3Q19>
 __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 {
+    constexpr int QL = LT::Q;        // velocities
+    constexpr int NYZ = nyz<LT>();   // those exchanged through LDS
+    constexpr int NXP = nxp<LT>();   // those with c_x = +1
+    constexpr int XP = LT::H + 1;    // the x-only direction (+1, 0, 0)
     using Cd = Codec<S>;
     using T = typename Cd::T;
     using R = typename Cd::R;
     using Sh = PairRingShape<M, TY, TZ>;
     constexpr int WZ = Sh::WZ, NC = Sh::NC, WZ2 = Sh::WZ2, NC2 = Sh::NC2;
     constexpr int NB1 = (M == 1) ? 2 : 1;
-    constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
+    constexpr uint32_t CXP = mask_cx<LT>(1), CXM = mask_cx<LT>(-1);
     static_assert(M == 1 || M == 2, "one or two merged steps");
     static_assert(sizeof(T) == 2 || sizeof(T) == 4, "32-bit arithmetic storages");
     static_assert(PF == 1 || PF == 2, "loads run one or two planes ahead");
 
     constexpr int SK = WALLS ? 64 : 0;  // each exchange buffer ends in a sink for ghost writes of lanes without a wall link
-    __shared__ R X1[NB1][16 * NC + SK];
-    __shared__ R X2[(M == 2) ? 16 * NC2 + SK : 1];
-    __shared__ R WT[WALLS ? Q : 1];  // moving-wall terms (entry q: received along c_q)
+    __shared__ R X1[NB1][NYZ * NC + SK];
+    __shared__ R X2[(M == 2) ? NYZ * NC2 + SK : 1];
+    __shared__ R WT[WALLS ? QL : 1];  // moving-wall terms (entry q: received along c_q)
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
@@ -312,16 +316,16 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     const bool has_next = !wallx || seg + 1 < a.nseg;
     const int nseg_next = (seg + 1 == a.nseg) ? 0 : seg + 1;
     const R omega = R(g.omega);
-    if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+    if constexpr (WALLS) wall_terms_to_l<LT>(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
     // receiving directions whose source lies beyond the moving face, for a
     // cell next to it (y or z face; an x face is handled per plane by xm)
     uint32_t mface = 0u;
     if constexpr (WALLS) {
-        sfor<1, Q>([&](auto qc) {
+        sfor<1, QL>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const int f = g.moving_face;
-            if ((f == 2 && cyq(q) == 1) || (f == 3 && cyq(q) == -1) || (f == 4 && czq(q) == 1) ||
-                (f == 5 && czq(q) == -1))
+            if ((f == 2 && LT::cy(q) == 1) || (f == 3 && LT::cy(q) == -1) || (f == 4 && LT::cz(q) == 1) ||
+                (f == 5 && LT::cz(q) == -1))
                 mface |= 1u << q;
         });
     }
@@ -373,10 +377,10 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         }
         if constexpr (WALLS) {
             uint32_t b = 0, mv = 0;
-            sfor<1, Q>([&](auto qc) {
+            sfor<1, QL>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                if constexpr (moves_yz(q)) {
-                    const int ys = y - cyq(q), zs = z - czq(q);
+                if constexpr (moves_yz_l<LT>(q)) {
+                    const int ys = y - LT::cy(q), zs = z - LT::cz(q);
                     int f1 = -1, f2 = -1;
                     if (g.wall[1] && ys < 0) f1 = 2;
                     if (g.wall[1] && ys >= g.ny) f1 = 3;
@@ -427,21 +431,21 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 
     // ---- pipeline registers ----
     using P2 = typename Buf2<T>::P;
-    P2 Lp[PF][Q];  // raw pair loads, PF planes in flight
-    T Lg[PF][Q];   // raw ring loads
+    P2 Lp[PF][QL];  // raw pair loads, PF planes in flight
+    T Lg[PF][QL];   // raw ring loads
     R Fl1[PF][K][3];
-    R acc1[K][Q], nxt1[K][5];  // step 1: pair and ring
-    R acc2[2][Q], nxt2[2][5];  // last step of M = 2: pair only
+    R acc1[K][QL], nxt1[K][NXP];  // step 1: pair and ring
+    R acc2[2][QL], nxt2[2][NXP];  // last step of M = 2: pair only
     R o1[K][3], o2[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             acc1[k][q] = R(0);
             if (k < 2) acc2[k][q] = R(0);
         }
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
+        for (int j = 0; j < NXP; ++j) {
             nxt1[k][j] = R(0);
             if (k < 2) nxt2[k][j] = R(0);
         }
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 #pragma unroll
     for (int b = 0; b < PF; ++b)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             Lp[b][q] = Buf2<T>::zero();
             Lg[b][q] = T(0);
         }
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     auto plane_base = [&](int xp, long long& qstride) -> const T* {
         if (a.inplace && xp >= e && has_next) {
             qstride = PL;
-            return side + ((long long)(nseg_next * M + (xp - e)) * Q) * PL;
+            return side + ((long long)(nseg_next * M + (xp - e)) * QL) * PL;
         }
         qstride = N;
         return f + (long long)wrapi(xp, g.nx) * PL;
@@ -489,13 +493,13 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             }
         }
     };
-    auto load_pair = [&](int xp, bool wanted, P2 (&L)[Q], R (&Fb)[K][3]) {
+    auto load_pair = [&](int xp, bool wanted, P2 (&L)[QL], R (&Fb)[K][3]) {
         const bool live = wanted && present(xp);
         long long qs;
         const T* bq = plane_base(xp, qs);
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             L[q] = Buf2<T>::ld(make_rsrc(bq, range), loffP);
             bq += qs;
         }
@@ -505,19 +509,19 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             load_force(xp, live, Fb[1], off1);
         }
     };
-    auto load_ring = [&](int xp, bool wanted, T (&L)[Q], R (&Fb)[K][3]) {
+    auto load_ring = [&](int xp, bool wanted, T (&L)[QL], R (&Fb)[K][3]) {
         const bool live = wanted && present(xp);
         long long qs;
         const T* bq = plane_base(xp, qs);
         uint32_t range = live ? plane_bytes : 0u, off = loffG;
         if (shell_w && !(a.inplace && xp >= e && has_next)) {  // (the side planes hold every row at time t)
             qs = (long long)M * g.nz;
-            bq = shell_w + (long long)wrapi(xp, g.nx) * Q * qs;
+            bq = shell_w + (long long)wrapi(xp, g.nx) * QL * qs;
             range = live ? uint32_t(qs) * uint32_t(sizeof(T)) : 0u;
             off = loffS;
         }
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             L[q] = Buf<T>::ld(make_rsrc(bq, range), off);
             bq += qs;
         }
@@ -572,11 +576,11 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         if (!__all(ok) && (tid & 63) == 0) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
-    auto store_pair = [&](const R (&v0)[Q], const R (&v1)[Q], int r, bool live) {
+    auto store_pair = [&](const R (&v0)[QL], const R (&v1)[QL], int r, bool live) {
         const T* bq = fo + (long long)(live ? r : 0) * PL;
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             if constexpr (sizeof(T) == 2)
                 Buf2<T>::st(Cd::enc2(v0[q], v1[q]), make_rsrc(bq, range), soffP);
             else
@@ -586,34 +590,34 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     };
 
     // step-1 collide of column k from its raw values (decoded here)
-    auto collide1 = [&](auto kc, R* X1w, const P2 (&LP)[Q], const T (&LG)[Q], const R (&Fb)[K][3]) {
+    auto collide1 = [&](auto kc, R* X1w, const P2 (&LP)[QL], const T (&LG)[QL], const R (&Fb)[K][3]) {
         constexpr int k = decltype(kc)::value;
-        R v[Q];
+        R v[QL];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             if constexpr (k < 2)
                 v[q] = Cd::dec(Buf2<T>::template get<k>(LP[q]));
             else
                 v[q] = Cd::dec(LG[q]);
         }
-        collide<R, FORCE>(v, omega, Fb[k][0], Fb[k][1], Fb[k][2]);
+        LT::template collide<R, FORCE>(v, omega, Fb[k][0], Fb[k][1], Fb[k][2]);
         // (with walls or a force, the slot address is rebuilt per plane rather
         // than kept live across the march: those variants are short of
         // registers, and a spilled address reloads behind the plane's loads)
         int sl = ((ci[k] & 1) ? NC / 2 : 0) + (ci[k] >> 1);
         if constexpr (WALLS || FORCE) sl = opaque(sl);
-        sfor<0, Q>([&](auto qc) {
+        sfor<0, QL>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            if constexpr (moves_yz(q)) X1w[yz_index(q) * NC + sl] = v[q];
+            if constexpr (moves_yz_l<LT>(q)) X1w[yz_index_l<LT>(q) * NC + sl] = v[q];
         });
         if constexpr (WALLS) {
             // level-1 receivers: the tile plus M-1 halo cells
             constexpr int PARk = (k == 0) ? (M & 1) : ((k == 1) ? ((M + 1) & 1) : -1);
-            if (rad[k] <= M - 1) ghost_out<R, PARk, NC, WZ>(v, nxt1[k], X1w, ci[k], byz[k], mlinks(byz[k]), WT, lane);
+            if (rad[k] <= M - 1) ghost_out<R, PARk, NC, WZ, LT>(v, nxt1[k], X1w, ci[k], byz[k], mlinks(byz[k]), WT, lane);
         }
         o1[k][0] = v[0];
         o1[k][1] = v[1];
-        o1[k][2] = v[10];
+        o1[k][2] = v[XP];
     };
 
     if constexpr (WALLS) __syncthreads();  // the wall-term table is complete
@@ -675,24 +679,24 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
                 constexpr int PAR = (k == 0) ? (M & 1) : ((k == 1) ? ((M + 1) & 1) : -1);  // parity of ci
                 constexpr int PAR2 = (k == 0) ? 1 : ((k == 1) ? 0 : -1);                 // parity of ci2
                 if (rad[k] <= 1) {
-                    complete_s<R, WALLS, PAR, NC, WZ>(acc1[k], X1w, ci[k], o1[k][1], xbd1);
+                    complete_s<R, WALLS, PAR, NC, WZ, LT>(acc1[k], X1w, ci[k], o1[k][1], xbd1);
                     if (coll2) {
-                        collide<R, FORCE>(acc1[k], omega, Fr[k][0], Fr[k][1], Fr[k][2]);
+                        LT::template collide<R, FORCE>(acc1[k], omega, Fr[k][0], Fr[k][1], Fr[k][2]);
                         int sl2 = split_at<PAR2, NC2 / 2>(ci2[k], 0);
                         if constexpr (WALLS || FORCE) sl2 = opaque(sl2);
-                        sfor<0, Q>([&](auto qc) {
+                        sfor<0, QL>([&](auto qc) {
                             constexpr int q = decltype(qc)::value;
-                            if constexpr (moves_yz(q)) X2[yz_index(q) * NC2 + sl2] = acc1[k][q];
+                            if constexpr (moves_yz_l<LT>(q)) X2[yz_index_l<LT>(q) * NC2 + sl2] = acc1[k][q];
                         });
                         if constexpr (WALLS && k < 2) {  // level-2 receivers: the tile
                             if (rad[k] == 0)
-                                ghost_out<R, PAR2, NC2, WZ2>(acc1[k], nxt2[k], X2, ci2[k], byz[k], mlinks(byz[k]), WT, lane);
+                                ghost_out<R, PAR2, NC2, WZ2, LT>(acc1[k], nxt2[k], X2, ci2[k], byz[k], mlinks(byz[k]), WT, lane);
                         }
                         o2[k][0] = acc1[k][0];
                         o2[k][1] = acc1[k][1];
-                        o2[k][2] = acc1[k][10];
+                        o2[k][2] = acc1[k][XP];
                     }
-                    deposit_s<R, WALLS, PAR, NC, WZ>(acc1[k], nxt1[k], X1w, ci[k], o1[k][0], o1[k][1], o1[k][2],
+                    deposit_s<R, WALLS, PAR, NC, WZ, LT>(acc1[k], nxt1[k], X1w, ci[k], o1[k][0], o1[k][1], o1[k][2],
                                                      xbn1, byz[k], mlinks(byz[k]) | xmn1, WT, X1w, lane);
                 }
             });
@@ -706,29 +710,29 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
             const bool act = rad[0] == 0;
             if constexpr (M == 2) {
                 if (act) {
-                    complete_s<R, WALLS, 1, NC2, WZ2>(acc2[0], X2, ci2[0], o2[0][1], xbd);
-                    complete_s<R, WALLS, 0, NC2, WZ2>(acc2[1], X2, ci2[1], o2[1][1], xbd);
+                    complete_s<R, WALLS, 1, NC2, WZ2, LT>(acc2[0], X2, ci2[0], o2[0][1], xbd);
+                    complete_s<R, WALLS, 0, NC2, WZ2, LT>(acc2[1], X2, ci2[1], o2[1][1], xbd);
                 }
                 if (storing) poll_finish(seen, i, r_out);
                 store_pair(acc2[0], acc2[1], r_out, storing);
                 if (act) {
-                    deposit_s<R, WALLS, 1, NC2, WZ2>(acc2[0], nxt2[0], X2, ci2[0], o2[0][0], o2[0][1], o2[0][2],
+                    deposit_s<R, WALLS, 1, NC2, WZ2, LT>(acc2[0], nxt2[0], X2, ci2[0], o2[0][0], o2[0][1], o2[0][2],
                                                      xbn, byz[0], mlinks(byz[0]) | xmn, WT, X2, lane);
-                    deposit_s<R, WALLS, 0, NC2, WZ2>(acc2[1], nxt2[1], X2, ci2[1], o2[1][0], o2[1][1], o2[1][2],
+                    deposit_s<R, WALLS, 0, NC2, WZ2, LT>(acc2[1], nxt2[1], X2, ci2[1], o2[1][0], o2[1][1], o2[1][2],
                                                      xbn, byz[1], mlinks(byz[1]) | xmn, WT, X2, lane);
                 }
             } else {
                 if (act) {
-                    complete_s<R, WALLS, 1, NC, WZ>(acc1[0], X1w, ci[0], o1[0][1], xbd);
-                    complete_s<R, WALLS, 0, NC, WZ>(acc1[1], X1w, ci[1], o1[1][1], xbd);
+                    complete_s<R, WALLS, 1, NC, WZ, LT>(acc1[0], X1w, ci[0], o1[0][1], xbd);
+                    complete_s<R, WALLS, 0, NC, WZ, LT>(acc1[1], X1w, ci[1], o1[1][1], xbd);
                 }
                 if (storing) poll_finish(seen, i, r_out);
                 store_pair(acc1[0], acc1[1], r_out, storing);
                 if (act) {
                     R* X1n = X1[(M == 1) ? ((i + 1) & 1) : 0];  // the buffer the next plane uses
-                    deposit_s<R, WALLS, 1, NC, WZ>(acc1[0], nxt1[0], X1w, ci[0], o1[0][0], o1[0][1], o1[0][2],
+                    deposit_s<R, WALLS, 1, NC, WZ, LT>(acc1[0], nxt1[0], X1w, ci[0], o1[0][0], o1[0][1], o1[0][2],
                                                    xbn, byz[0], mlinks(byz[0]) | xmn, WT, X1n, lane);
-                    deposit_s<R, WALLS, 0, NC, WZ>(acc1[1], nxt1[1], X1w, ci[1], o1[1][0], o1[1][1], o1[1][2],
+                    deposit_s<R, WALLS, 0, NC, WZ, LT>(acc1[1], nxt1[1], X1w, ci[1], o1[1][0], o1[1][1], o1[1][2],
                                                    xbn, byz[1], mlinks(byz[1]) | xmn, WT, X1n, lane);
                 }
             }
@@ -742,23 +746,23 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
     }
 }
 
-template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF, class LT = D3Q19>
 hipError_t launch_march_pr_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
 {
-    auto kern = k_march_pr<S, M, TY, TZ, WALLS, FORCE, PF>;
+    auto kern = k_march_pr<S, M, TY, TZ, WALLS, FORCE, PF, LT>;
     MarchArgs arg = a;
     void* params[] = {&arg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks),
                                       dim3(PairRingShape<M, TY, TZ>::NT), params, 0, st);
 }
 
-template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF>
+template <int S, int M, int TY, int TZ, bool WALLS, bool FORCE, int PF, class LT = D3Q19>
 int max_blocks_pr_shape()
 {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_pr<S, M, TY, TZ, WALLS, FORCE, PF>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_pr<S, M, TY, TZ, WALLS, FORCE, PF, LT>,
                                                      PairRingShape<M, TY, TZ>::NT, 0) != hipSuccess)
         return 0;
     return per_cu * cus;

@@ -23,6 +23,10 @@ CASES = [
     ((17, 41, 33), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
     ((26, 13, 70), (MOVING_WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.04, 0.01)),
     ((6, 5, 7), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),  # one tile smaller than the halo frame
+    # even nz: D3Q15 in FP32 takes the pair-and-ring layout
+    ((19, 35, 130), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((20, 37, 68), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, -0.02)),
+    ((12, 18, 6), (PERIODIC, PERIODIC, WALL, WALL, MOVING_WALL, WALL), (0.03, -0.02, 0.0)),
 ]
 
 
@@ -73,7 +77,7 @@ def test_sets_match_the_oracle_and_schemes_agree(q, storage, tol, case):
 
 @pytest.mark.parametrize("q", [15, 27])
 def test_sets_with_a_body_force(q):
-    shape = (24, 20, 18)
+    shape = (24, 20, 18)  # even nz: the pair-and-ring layout for D3Q15
     faces = (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL)
     rho0, u0 = _init(shape, 700)
     F = wl.normal_field(shape, 1e-4, 701)
@@ -121,8 +125,8 @@ def test_sets_run_without_allocation_too():
     lat.close()
 
 
-@pytest.mark.parametrize("q,variant", [(15, 1), (15, 2), (27, 1)])
-@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("q,variant", [(15, 1), (15, 2), (15, 3), (27, 1)])
+@pytest.mark.parametrize("case", [0, 1, 5, 6])
 def test_set_tile_variants_equal_two_array_bitwise(q, variant, case):
     # the larger FP32 tiles (two or three columns per thread)
     shape, faces, wall_u = CASES[case]

@@ -144,7 +144,7 @@ def test_velocity_sets_sizes_and_limits():
     for q in (15, 27):
         assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q))[0] == capi.LBM_EUNSUPPORTED
         assert _status(_cfg(scheme=capi.LBM_SWAP3, velocities=q))[0] == capi.LBM_EUNSUPPORTED
-        assert _status(_cfg(velocities=q, variant=3))[0] == capi.LBM_EUNSUPPORTED
+        assert _status(_cfg(velocities=q, variant=4))[0] == capi.LBM_EUNSUPPORTED
         # a plane of more tiles than co-resident workgroups would need rounds
         assert _status(_cfg(shape=(8, 1024, 1024), velocities=q))[0] == capi.LBM_EUNSUPPORTED
     assert _status(_cfg(velocities=20))[0] == capi.LBM_EINVAL

@@ -31,9 +31,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           f"-I{os.path.join(os.path.dirname(HERE), 'include')}"]
 
 
-# the sources the marching kernels and their launch are built from
+# the sources the marching kernels and their launch configuration are built
+# from (the kernels' code and the host's choice of shape, segments and grid)
 MARCH_SOURCES = ("d3q19.hpp", "lattices.hpp", "lbm_internal.hpp", "march.hpp", "march_pr.hpp", "march_dispatch.hpp",
-                 "march_f32.hip", "march_f16.hip", "march_bf16.hip", "march_f64.hip", "lbm_api.cpp", "k_basic.hip")
+                 "march_sets.hpp", "march_f32.hip", "march_f16.hip", "march_bf16.hip", "march_f64.hip", "lbm_api.cpp")
 
 
 def source_digest(names=MARCH_SOURCES) -> str:

@@ -88,23 +88,41 @@ __global__ __launch_bounds__(256) void k_two_array(Geom g, const typename Codec<
 // every segment and clear the progress counters (flags[0] is the timeout
 // word, flags[(1 + w) * fstride] the counter of work item w).
 // ------------------------------------------------------------------------
+// One contiguous run of len values, copied by the blocks of one grid row:
+// 16-byte accesses when the caller has checked that both runs are 16-byte
+// aligned and len is a whole number of 16-byte units.
+template <class T>
+__device__ __forceinline__ void copy_run(const T* __restrict__ src, T* __restrict__ dst, long long len, bool vec)
+{
+    const long long t0 = (long long)blockIdx.x * 256 + threadIdx.x, stride = (long long)gridDim.x * 256;
+    if (vec) {
+        const long long n16 = len * (long long)sizeof(T) / 16;
+        const uint4* __restrict__ s4 = reinterpret_cast<const uint4*>(src);
+        uint4* __restrict__ d4 = reinterpret_cast<uint4*>(dst);
+        for (long long i = t0; i < n16; i += stride) d4[i] = s4[i];
+    } else {
+        for (long long i = t0; i < len; i += stride) dst[i] = src[i];
+    }
+}
+
+// Grid rows walk the runs (run it = (b * M + j) * Q + q: plane j of segment b,
+// direction q, one y-z plane long); the blocks of a row split the run.
 template <class T>
 __global__ __launch_bounds__(256) void k_prepass(Geom g, const T* __restrict__ f, T* __restrict__ side, int* flags,
-                                                 int nflags, int fstride, int M, int seg_len, int nseg)
+                                                 int nflags, int fstride, int M, int seg_len, int nseg, int vec)
 {
-    const long long per = (long long)g.lat * g.PL;
-    const long long total = (long long)nseg * M * per;
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-        const long long bj = t / per, rem = t - bj * per;
-        const long long q = rem / g.PL, o = rem - q * g.PL;
-        const int b = int(bj / M), j = int(bj - (long long)b * M);
+    const int nitems = nseg * M * g.lat;
+    for (int it = blockIdx.y; it < nitems; it += gridDim.y) {
+        const int q = it % g.lat, bj = it / g.lat;
+        const int b = bj / M, j = bj - b * M;
         const int plane = (b * seg_len + j) % g.nx;
-        side[t] = f[q * g.N + (long long)plane * g.PL + o];
+        copy_run(f + (long long)q * g.N + (long long)plane * g.PL, side + (long long)it * g.PL, g.PL, vec != 0);
     }
     // progress counters 1 .. nflags-1; word 0, the timeout report, is left as
     // it is: it stays set once any pass of the context has timed out
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x + 1; t < nflags; t += (long long)gridDim.x * 256)
-        flags[t * fstride] = 0;
+    if (blockIdx.y == 0)
+        for (long long t = (long long)blockIdx.x * 256 + threadIdx.x + 1; t < nflags; t += (long long)gridDim.x * 256)
+            flags[t * fstride] = 0;
 }
 
 __global__ __launch_bounds__(64) void k_clear_word(int* w)
@@ -282,16 +300,31 @@ hipError_t launch_copy(int storage, const Geom& g, const void* src, void* dst, h
     return hipMemcpyAsync(dst, src, size_t(g.lat) * size_t(g.N) * elem, hipMemcpyDeviceToDevice, s);
 }
 
+static bool aligned16(const void* p)
+{
+    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Grid for nitems runs of `units` copy units each: rows walk the runs, about
+// four units per thread along a row.
+static dim3 run_grid(long long units, int nitems)
+{
+    long long bx = (units + 1023) / 1024;
+    if (bx < 1) bx = 1;
+    if (bx > 1024) bx = 1024;
+    const int by = nitems < 1 ? 1 : (nitems > 65535 ? 65535 : nitems);
+    return dim3(unsigned(bx), unsigned(by));
+}
+
 template <class T>
 static hipError_t prepass_t(const Geom& g, const MarchPlan& p, const void* f, void* side, int* flags, hipStream_t s)
 {
-    const long long total = (long long)p.nseg * p.M * g.lat * g.PL;
-    long long blocks = (total + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 16384) blocks = 16384;
+    const int nitems = p.nseg * p.M * g.lat;
+    const bool vec = (g.PL * (long long)sizeof(T)) % 16 == 0 && aligned16(f) && aligned16(side);
+    const dim3 grid = run_grid(vec ? g.PL * (long long)sizeof(T) / 16 : g.PL, nitems);
     const int nflags = p.nty * p.ntz * p.nseg + 1;  // every tile of every round, and the timeout word
-    hipLaunchKernelGGL(k_prepass<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
-                       static_cast<T*>(side), flags, nflags, p.flag_stride, p.M, p.seg_len, p.nseg);
+    hipLaunchKernelGGL(k_prepass<T>, grid, dim3(256), 0, s, g, static_cast<const T*>(f), static_cast<T*>(side), flags,
+                       nflags, p.flag_stride, p.M, p.seg_len, p.nseg, int(vec));
     return hipGetLastError();
 }
 
@@ -300,35 +333,31 @@ static hipError_t prepass_t(const Geom& g, const MarchPlan& p, const void* f, vo
 // band's first M rows, part 1 its last M rows.
 template <class T>
 __global__ __launch_bounds__(256) void k_shells(Geom g, const T* __restrict__ f, T* __restrict__ shell, int M,
-                                                int band_rows, int nbands)
+                                                int band_rows, int nbands, int vec)
 {
-    const long long rowlen = (long long)M * g.nz;
-    const long long total = (long long)nbands * 2 * g.nx * g.lat * rowlen;
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-        long long r = t;
-        const int z = int(r % g.nz);
-        r /= g.nz;
-        const int row = int(r % M);
-        r /= M;
-        const int q = int(r % g.lat);
+    const long long len = (long long)M * g.nz;  // M consecutive rows: one contiguous run of the lattice
+    const int nitems = nbands * 2 * g.nx * g.lat;
+    for (int it = blockIdx.y; it < nitems; it += gridDim.y) {
+        int r = it;
+        const int q = r % g.lat;
         r /= g.lat;
-        const int x = int(r % g.nx);
+        const int x = r % g.nx;
         r /= g.nx;
-        const int part = int(r % 2), band = int(r / 2);
+        const int part = r % 2, band = r / 2;
         const int y0 = band * band_rows, y1 = min(g.ny, y0 + band_rows);
-        const int y = part == 0 ? y0 + row : y1 - M + row;
-        shell[t] = f[q * g.N + ((long long)x * g.ny + y) * g.nz + z];
+        const int y = part == 0 ? y0 : y1 - M;
+        copy_run(f + (long long)q * g.N + ((long long)x * g.ny + y) * g.nz, shell + (long long)it * len, len, vec != 0);
     }
 }
 
 template <class T>
 static hipError_t shells_t(const Geom& g, const MarchPlan& p, int TY, const void* f, void* shell, hipStream_t s)
 {
-    const long long total = (long long)p.nbands * 2 * g.nx * g.lat * p.M * g.nz;
-    long long blocks = (total + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_shells<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g, static_cast<const T*>(f),
-                       static_cast<T*>(shell), p.M, p.nty_band * TY, p.nbands);
+    const int nitems = p.nbands * 2 * g.nx * g.lat;
+    const long long len = (long long)p.M * g.nz;
+    const bool vec = (g.nz * (long long)sizeof(T)) % 16 == 0 && aligned16(f) && aligned16(shell);
+    hipLaunchKernelGGL(k_shells<T>, run_grid(vec ? len * (long long)sizeof(T) / 16 : len, nitems), dim3(256), 0, s, g,
+                       static_cast<const T*>(f), static_cast<T*>(shell), p.M, p.nty_band * TY, p.nbands, int(vec));
     return hipGetLastError();
 }
 

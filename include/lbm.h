@@ -101,8 +101,8 @@ typedef struct {
                            LBM_SWAP1 and LBM_SWAP2, planes that fit one round, no adjoint or probes */
 } lbm_config;
 
-/* Bytes the caller must provide for the distribution buffer (19*N values of
- * the storage type: the single copy of Sec. 3, which the in-place schemes
+/* Bytes the caller must provide for the distribution buffer (Q*N values of
+ * the storage type, Q = 19 for D3Q19: the single copy of Sec. 3, which the in-place schemes
  * update without a second lattice) and for the work buffer of this
  * configuration (the saved planes that stand in for the bounding-box stages of
  * Alg. 1 and the slab borders of Sec. 4.2, progress counters, reduction
@@ -163,7 +163,7 @@ lbm_status lbm_step_static(const lbm_config* cfg, void* f_dev, const void* force
 
 /* Advance k in {1, 2} steps from the state f_src into f_dst, out of place:
  * f_src is read only and the context's own distribution buffer is neither
- * read nor changed.  Both buffers have the size and layout of f (19N values
+ * read nor changed.  Both buffers have the size and layout of f (Q*N values
  * of the storage type), must not overlap and must be 256-byte aligned.  With
  * LBM_SWAP2 and k = 2 this is one merged pass, the same kernel and the same
  * bytes moved as an in-place pass (no side planes or progress counters are

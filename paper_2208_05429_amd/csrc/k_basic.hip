@@ -288,8 +288,9 @@ hipError_t launch_two_array(int storage, bool force, const Geom& g, const void* 
     switch (storage) {
     case ST_F64: return force ? two_array_s<ST_F64, true>(g, src, dst, F, s) : two_array_s<ST_F64, false>(g, src, dst, F, s);
     case ST_F32: return force ? two_array_s<ST_F32, true>(g, src, dst, F, s) : two_array_s<ST_F32, false>(g, src, dst, F, s);
-    case ST_F16: return force ? hipErrorInvalidValue : two_array_s<ST_F16, false>(g, src, dst, F, s);
-    case ST_BF16: return force ? hipErrorInvalidValue : two_array_s<ST_BF16, false>(g, src, dst, F, s);
+    case ST_F16: return force ? two_array_s<ST_F16, true>(g, src, dst, F, s) : two_array_s<ST_F16, false>(g, src, dst, F, s);
+    case ST_BF16:
+        return force ? two_array_s<ST_BF16, true>(g, src, dst, F, s) : two_array_s<ST_BF16, false>(g, src, dst, F, s);
     }
     return hipErrorInvalidValue;
 }
@@ -422,8 +423,12 @@ hipError_t launch_macro(int storage, bool force, const Geom& g, const void* f, c
     case ST_F32:
         return force ? macro_s<ST_F32, true>(g, f, F, rho, u, unorm, partials, sums, s)
                      : macro_s<ST_F32, false>(g, f, F, rho, u, unorm, partials, sums, s);
-    case ST_F16: return macro_s<ST_F16, false>(g, f, F, rho, u, unorm, partials, sums, s);
-    case ST_BF16: return macro_s<ST_BF16, false>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_F16:
+        return force ? macro_s<ST_F16, true>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_F16, false>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_BF16:
+        return force ? macro_s<ST_BF16, true>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_BF16, false>(g, f, F, rho, u, unorm, partials, sums, s);
     }
     return hipErrorInvalidValue;
 }

@@ -279,8 +279,6 @@ lbm_status validate(const lbm_config* c, std::string* why)
     if (moving > 1) return fail(why, LBM_EINVAL, "at most one moving-wall face");
     for (int a = 0; a < 3; ++a)
         if (!isfinite(c->wall_u[a])) return fail(why, LBM_EINVAL, "wall velocity must be finite");
-    if (c->use_force && c->storage != LBM_F64 && c->storage != LBM_F32)
-        return fail(why, LBM_EUNSUPPORTED, "a body force is built for FP64 and FP32 storage only");
     if (c->variant < 0) return fail(why, LBM_EINVAL, "variant must be >= 0");
     if (c->velocities != 0 && c->velocities != 15 && c->velocities != 19 && c->velocities != 27)
         return fail(why, LBM_EINVAL, "velocities must be 0 (D3Q19), 15, 19 or 27");

@@ -39,7 +39,6 @@ def _status(cfg):
     (dict(faces=(capi.LBM_WALL, capi.LBM_PERIODIC, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(faces=(capi.LBM_MOVING_WALL, capi.LBM_MOVING_WALL, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
-    (dict(storage=capi.LBM_F16_OFS, use_force=True), capi.LBM_EUNSUPPORTED),
     (dict(variant=99), capi.LBM_EUNSUPPORTED),
     # rounds across a periodic y seam: a last tile row thinner than the halo for
     # every tile height built (16 and 32 rows)
@@ -57,6 +56,8 @@ def test_buffer_sizes():
     for storage, s in ((capi.LBM_F64, 8), (capi.LBM_F32, 4), (capi.LBM_F16_OFS, 2), (capi.LBM_BF16_OFS, 2)):
         st, fb, wb = _status(_cfg(storage=storage))
         assert st == capi.LBM_OK and fb == 19 * 32 ** 3 * s and wb > 0
+        for scheme in (capi.LBM_TWO_ARRAY, capi.LBM_SWAP1, capi.LBM_SWAP2):  # a body force with every storage
+            assert _status(_cfg(storage=storage, scheme=scheme, use_force=True))[0] == capi.LBM_OK
     st, fb, wb = _status(_cfg(scheme=capi.LBM_TWO_ARRAY))
     assert st == capi.LBM_OK and wb >= fb  # the plain scheme's second lattice lives in the work buffer
     st, fb, wb2 = _status(_cfg(scheme=capi.LBM_SWAP2))

@@ -273,8 +273,9 @@ def test_rounds_with_force_match_two_array_bitwise(storage):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("case", [0, 1, 3, 4, 5, 6])
-def test_rounds_16bit_in_place_matches_out_of_place(storage, case):
+@pytest.mark.parametrize("case,force", [(0, False), (1, False), (3, False), (4, False), (5, False), (6, False),
+                                        (1, True), (4, True)])
+def test_rounds_16bit_in_place_matches_out_of_place(storage, case, force):
     # 16-bit offset storage in rounds: the saved band boundary rows are raw
     # 16-bit codes.  The merged pass rounds to 16 bits once per two steps (the
     # plain kernels every step), so the reference is the same merged pass run
@@ -284,8 +285,9 @@ def test_rounds_16bit_in_place_matches_out_of_place(storage, case):
     rho0, u0 = wl.taylor_green_3d(shape, 0.03)
     u0 = u0 + wl.uniform_noise(shape, 5e-3, 420 + case)
     r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 421 + case)), torch.as_tensor(u0)
-    print(f"[gpu] rounds {storage} {shape} {names}", flush=True)
-    lat = Lattice(shape, 0.6, storage, "swap2", names, wall_u, rho0=r0, u0=v0)
+    F = torch.as_tensor(wl.normal_field(shape, 1e-4, 422 + case)) if force else None
+    print(f"[gpu] rounds {storage} {shape} {names} force {force}", flush=True)
+    lat = Lattice(shape, 0.6, storage, "swap2", names, wall_u, force=F, rho0=r0, u0=v0)
     a, b = torch.empty_like(lat.f), torch.empty_like(lat.f)
     lat.step_into(lat.f, a, 2)
     lat.step_into(a, b, 2)

@@ -77,9 +77,10 @@ def _half_ulp(x, storage):
     return 0.5 * 2.0 ** (e - 7)
 
 
+@pytest.mark.parametrize("force", [False, True])
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("scheme,steps", [("swap1", 1), ("swap2", 2), ("two_array", 1)])
-def test_one_16bit_store_is_within_half_an_ulp_of_the_oracle(storage, scheme, steps):
+def test_one_16bit_store_is_within_half_an_ulp_of_the_oracle(storage, scheme, steps, force):
     from oracle import MOVING_WALL, WALL, Oracle
     from paper_2208_05429_amd.lattice import lattice_weights
     shape = (12, 20, 70)
@@ -89,19 +90,22 @@ def test_one_16bit_store_is_within_half_an_ulp_of_the_oracle(storage, scheme, st
     rho0, u0 = wl.taylor_green_3d(shape, 0.03)
     u0 = u0 + wl.uniform_noise(shape, 5e-3, 480)
     rho0 = wl.random_density(shape, 0.01, 481)
-    print(f"[gpu] one {storage} store, {scheme}, {steps} step(s)", flush=True)
-    lat = Lattice(shape, 0.7, storage, scheme, names, wall_u, rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0))
+    # a body force (Guo forcing) is read in FP32: the oracle gets the same FP32 values
+    F = wl.normal_field(shape, 1e-3, 482).astype(np.float32).astype(np.float64) if force else None
+    print(f"[gpu] one {storage} store, {scheme}, {steps} step(s), force {force}", flush=True)
+    lat = Lattice(shape, 0.7, storage, scheme, names, wall_u, force=None if F is None else torch.as_tensor(F),
+                  rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0))
     f0 = lat.distributions()  # the decoded 16-bit state: exact in FP64
     lat.step(steps)
     torch.cuda.synchronize()
     w = lattice_weights()[:, None, None, None]
     g_gpu = lat.distributions() - w
     o = Oracle(shape, 0.7, faces=faces, wall_u=wall_u)
-    g_ref = o.run(np.ascontiguousarray(f0), steps) - w
+    g_ref = o.run(np.ascontiguousarray(f0), steps, F) - w
     err = np.abs(g_gpu - g_ref)
     # (the binade of the larger of the two: rounding up across a power of two)
     bound = _half_ulp(np.maximum(np.abs(g_ref), np.abs(g_gpu)), storage) * (1 + 1e-3) + 2e-7
     worst = float((err / bound).max())
-    print(f"{storage} {scheme}: max |g - g_ref| = {err.max():.3e}, max err/bound = {worst:.3f}")
+    print(f"{storage} {scheme} force {force}: max |g - g_ref| = {err.max():.3e}, max err/bound = {worst:.3f}")
     assert worst <= 1.0, worst
     lat.close()

@@ -63,7 +63,7 @@ typedef struct lbm_ctx lbm_ctx;
 typedef enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,       /* bad argument: tau <= 1/2, dims < 1, null pointer, bad face codes */
-    LBM_EUNSUPPORTED = -2, /* valid but not built: e.g. adjoint with 16-bit storage */
+    LBM_EUNSUPPORTED = -2, /* valid but not built: e.g. the adjoint of D3Q15/D3Q27 */
     LBM_EDEVICE = -3,      /* a HIP call or kernel launch failed; message kept */
     LBM_ESTATE = -4        /* call on a NULL or failed context */
 } lbm_status;
@@ -188,7 +188,8 @@ lbm_status lbm_macroscopic(lbm_ctx* ctx, double* rho_dev, double* u_dev, double*
  * f_dev (grad_u_dev: 3N of the arithmetic type), write lambda = dL/df
  * (lambda_dev: 19N of the arithmetic type, not offset) and add the direct
  * dL/dF = dL/du / (2 rho) to grad_force_dev (3N; may be NULL without a force).
- * Supported for LBM_F64 and LBM_F32 storage. */
+ * Every storage (16-bit states are decoded; lambda and gradients are FP32);
+ * D3Q19 only (LBM_EUNSUPPORTED otherwise). */
 lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u_dev, void* lambda_dev,
                              void* grad_force_dev);
 
@@ -202,8 +203,10 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
  * target (the own lambda of the opposite direction on a wall link), then the
  * transposed collision acts per cell.  With k = 2 the state f_{t+1} is
  * recomputed on chip, so one call reads f_t once: the adjoint of the two-step
- * merged pass of Sec. 4.1 (132 bytes per lattice update at FP32).  FP64 and
- * FP32 storage only (LBM_EUNSUPPORTED otherwise). */
+ * merged pass of Sec. 4.1 (132 bytes per lattice update at FP32).  Every
+ * storage: with FP16/BF16 the state is decoded and the adjoint computes in
+ * FP32, the adjoint of the FP32 arithmetic between 16-bit stores (rounding
+ * has no useful derivative).  D3Q19 only (LBM_EUNSUPPORTED otherwise). */
 lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambda_in_dev, void* lambda_out_dev,
                             void* grad_force_dev, int32_t k);
 

@@ -139,6 +139,12 @@ hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const vo
     case ST_F32:
         return force ? macro_adjoint_s<ST_F32, true>(g, f, F, grad_u, lambda, grad_force, s)
                      : macro_adjoint_s<ST_F32, false>(g, f, F, grad_u, lambda, grad_force, s);
+    case ST_F16:
+        return force ? macro_adjoint_s<ST_F16, true>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_F16, false>(g, f, F, grad_u, lambda, grad_force, s);
+    case ST_BF16:
+        return force ? macro_adjoint_s<ST_BF16, true>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_BF16, false>(g, f, F, grad_u, lambda, grad_force, s);
     }
     return hipErrorInvalidValue;
 }
@@ -175,6 +181,12 @@ hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, co
     case ST_F32:
         return force ? adjoint1_s<ST_F32, true>(g, f_t, F, lam_in, lam_out, grad_force, s)
                      : adjoint1_s<ST_F32, false>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F16:
+        return force ? adjoint1_s<ST_F16, true>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_F16, false>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_BF16:
+        return force ? adjoint1_s<ST_BF16, true>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_BF16, false>(g, f_t, F, lam_in, lam_out, grad_force, s);
     }
     return hipErrorInvalidValue;
 }

@@ -392,22 +392,30 @@ static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, c
     return hipGetLastError();
 }
 
+// FP32 arithmetic (32- and 16-bit storage).  Each tile is one 512-thread
+// workgroup per plane, so the plane takes the tiling with fewer tiles.
+// 12 x 28 (its 16 x 32 frame of tile plus two halo cells fills the workgroup
+// exactly; 16 % faster than 16 x 16 at 256^3) unless its ragged edge tiles
+// make 16 x 16 cheaper (a 64 x 64 plane: 18 tiles against 16).  The choice
+// depends on the lattice only, so every storage takes the same tiles.
+template <int S>
+static hipError_t adjoint2_r32(const Geom& g, const void* f_t, const void* F, const void* lam_in, void* lam_out,
+                               void* grad_force, hipStream_t s)
+{
+    const long long t1228 = (long long)((g.ny + 11) / 12) * ((g.nz + 27) / 28);
+    const long long t1616 = (long long)((g.ny + 15) / 16) * ((g.nz + 15) / 16);
+    if (t1616 < t1228) return adjoint2_shape<S, 16, 16, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    return adjoint2_shape<S, 12, 28, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+}
+
 hipError_t launch_step_adjoint2(int storage, const Geom& g, const void* f_t, const void* F, const void* lam_in,
                                 void* lam_out, void* grad_force, hipStream_t s)
 {
     switch (storage) {
     case ST_F64: return adjoint2_shape<ST_F64, 8, 8, 256>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    case ST_F32: {
-        // Each tile is one 512-thread workgroup per plane, so the plane takes
-        // the tiling with fewer tiles.  12 x 28 (its 16 x 32 frame of tile
-        // plus two halo cells fills the workgroup exactly; 16 % faster than
-        // 16 x 16 at 256^3) unless its ragged edge tiles make 16 x 16 cheaper
-        // (a 64 x 64 plane: 18 tiles against 16).
-        const long long t1228 = (long long)((g.ny + 11) / 12) * ((g.nz + 27) / 28);
-        const long long t1616 = (long long)((g.ny + 15) / 16) * ((g.nz + 15) / 16);
-        if (t1616 < t1228) return adjoint2_shape<ST_F32, 16, 16, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
-        return adjoint2_shape<ST_F32, 12, 28, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    }
+    case ST_F32: return adjoint2_r32<ST_F32>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F16: return adjoint2_r32<ST_F16>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_BF16: return adjoint2_r32<ST_BF16>(g, f_t, F, lam_in, lam_out, grad_force, s);
     }
     return hipErrorInvalidValue;
 }

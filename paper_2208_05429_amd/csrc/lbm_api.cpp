@@ -764,8 +764,6 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
 {
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
     ctx->err.clear();
-    if (ctx->cfg.storage != LBM_F64 && ctx->cfg.storage != LBM_F32)
-        return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for FP64 and FP32 storage only");
     if (ctx->g.lat != 19) return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for D3Q19 only");
     if (!f_dev || !grad_u_dev || !lambda_dev) return fail(&ctx->err, LBM_EINVAL, "f, grad_u and lambda are required");
     if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
@@ -780,8 +778,6 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
 {
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
     ctx->err.clear();
-    if (ctx->cfg.storage != LBM_F64 && ctx->cfg.storage != LBM_F32)
-        return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for FP64 and FP32 storage only");
     if (ctx->g.lat != 19) return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for D3Q19 only");
     if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
     if (!f_t_dev || !lambda_in_dev || !lambda_out_dev)

@@ -231,6 +231,69 @@ def test_force_gradient_does_not_depend_on_the_forward_scheme(storage):
         assert torch.equal(g, g0), (scheme, (g - g0).abs().max().item())
 
 
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("shape", [(10, 13, 12), (9, 30, 70)])
+def test_16bit_adjoint_equals_fp32_adjoint_on_the_decoded_state(storage, shape):
+    # A 16-bit offset decodes exactly into FP32 and the adjoint computes in
+    # FP32 for both storages, so on the same decoded state the seed, one
+    # reverse step and two merged reverse steps (f_{t+1} recomputed on chip)
+    # equal the FP32 ones bit for bit; the FP32 adjoint is held to the
+    # oracle's above.  (10, 13, 12) takes 16 x 16 merged-adjoint tiles,
+    # (9, 30, 70) 12 x 28 ones (several, with ragged edges).
+    rho0, u0 = _init(shape, 21)
+    F = torch.as_tensor(wl.normal_field(shape, 1e-4, 22))
+    print(f"[gpu] 16-bit adjoint {storage} {shape}", flush=True)
+    lat16 = Lattice(shape, 0.8, storage, "swap2", NAMES, force=F, rho0=torch.as_tensor(rho0),
+                    u0=torch.as_tensor(u0))
+    lat16.step(3)
+    lat32 = Lattice(shape, 0.8, "f32", "swap2", NAMES, force=F, f=lat16.f.to(torch.float32).contiguous())
+    torch.cuda.synchronize()
+    gu = torch.as_tensor(wl.normal_field(shape, 1e-2, 23), dtype=torch.float32, device="cuda").contiguous()
+    lam_next = torch.as_tensor(wl.normal_field(shape, 1.0, 24, comps=19), dtype=torch.float32,
+                               device="cuda").contiguous()
+
+    def adjoints(lat):
+        lam = torch.empty((19,) + shape, dtype=torch.float32, device="cuda")
+        gF = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
+        capi.lbm_macro_adjoint(lat.ctx, lat.f.data_ptr(), gu.data_ptr(), lam.data_ptr(), gF.data_ptr())
+        out = [lam, gF]
+        for k in (1, 2):
+            lout = torch.empty_like(lam_next)
+            g = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
+            capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lam_next.data_ptr(), lout.data_ptr(), g.data_ptr(), k)
+            out += [lout, g]
+        torch.cuda.synchronize()
+        return out
+
+    names = ("seed lambda", "seed dL/dF", "1 step lambda", "1 step dL/dF", "2 steps lambda", "2 steps dL/dF")
+    for name, x, y in zip(names, adjoints(lat16), adjoints(lat32)):
+        assert torch.isfinite(x).all() and x.abs().max() > 0, name
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32)), (name, (x - y).abs().max().item())
+    lat16.close()
+    lat32.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_force_gradient_does_not_depend_on_the_checkpoint_interval(storage):
+    # Through autograd with 16-bit storage: with merged passes every even
+    # interval reaches the same 16-bit states (in place, out of place or
+    # recomputed: bitwise equal), so the gradient is the same to the bit.
+    # (Single-step and merged passes round differently in 16 bits.)
+    shape, steps = (16, 12, 10), 12
+    o, f0, F, ut, f0_dev = _channel_problem(shape, steps, storage)
+    Fd, utd = torch.as_tensor(F, device="cuda"), torch.as_tensor(ut, device="cuda")
+    out = {}
+    for ck in (2, 4, 6, 12):
+        spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=ck, merged=True)
+        out[ck] = force_gradient(Fd, f0_dev, spec, utd)
+    L0, g0 = out[2]
+    assert torch.isfinite(g0).all() and g0.abs().max() > 0
+    for ck in (4, 6, 12):
+        L, g = out[ck]
+        assert L == L0, ck
+        assert torch.equal(g, g0), (ck, (g - g0).abs().max().item())
+
+
 def test_step_adjoint_rejects_overlapping_lambda():
     shape = (8, 16, 16)
     lat = Lattice(shape, 0.8, "f32", "swap2")

@@ -137,8 +137,24 @@ bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPl
 
 // A plain-layout shape for M steps whose last tile row across a periodic y
 // seam is at least as thick as the halo (or whole), in table order.
-bool plain_shape_for_seam(int storage, int M, int ny, MarchPlan* r)
+bool plain_shape_for_seam(int storage, int M, int ny, MarchPlan* r, int lat = 19)
 {
+    if (lat != 19) {
+        if (M > 2) return false;
+        for (const SetShapes& e : kSetShapes) {
+            const ShapeEntry& t = M == 2 ? e.m2 : e.m1;
+            if (e.lat != lat || e.storage != storage || t.pr) continue;
+            const int rem = ny % t.TY;
+            if (rem != 0 && rem < M) continue;
+            r->TY = t.TY;
+            r->TZ = t.TZ;
+            r->NT = t.NT;
+            r->pr = 0;
+            r->pf = 1;
+            return true;
+        }
+        return false;
+    }
     if (M == 3 && storage != LBM_F32) return false;
     const ShapeEntry* tab = M == 3 ? kShapesM3F32 : (storage == LBM_F64 ? kShapesF64 : kShapesF32);
     const int n = M == 3 ? int(sizeof(kShapesM3F32) / sizeof(ShapeEntry))
@@ -174,7 +190,7 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
         // only above a whole tile row; the plain layout of the same tile also
         // takes a ragged last row (if it is at least as thick as the halo).
         MarchPlan q = r;
-        if (march_shape_of(c.storage, M, c.variant, c.nz, true, &q)) {
+        if (march_shape_of(c.storage, M, c.variant, c.nz, true, &q, lat)) {
             r = q;
             r.nty = (c.ny + r.TY - 1) / r.TY;
             r.ntz = (c.nz + r.TZ - 1) / r.TZ;
@@ -184,7 +200,7 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
         // that last row would be thinner than the halo: another plain tile
         // height may leave a thick enough one
         MarchPlan q = r;
-        if (plain_shape_for_seam(c.storage, M, c.ny, &q)) {
+        if (plain_shape_for_seam(c.storage, M, c.ny, &q, lat)) {
             r = q;
             r.nty = (c.ny + r.TY - 1) / r.TY;
             r.ntz = (c.nz + r.TZ - 1) / r.TZ;
@@ -193,10 +209,6 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     const int tiles = r.nty * r.ntz;
     r.nbands = 1;
     r.nty_band = r.nty;
-    if (tiles > cap && lat != 19)
-        return fail(why, LBM_EUNSUPPORTED,
-                    "the y-z plane needs more marching workgroups than can be co-resident; rounds over bands of tile "
-                    "rows are built for D3Q19 only");
     if (tiles > cap) {
         // rounds over bands of tile rows, each band's boundary rows saved first
         auto need = [&]() {
@@ -245,7 +257,7 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
     r.cap = cap;
     r.side_bytes = size_t(nseg) * size_t(M) * size_t(lat) * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
-    r.shell_bytes = r.nbands > 1 ? size_t(r.nbands) * 2u * size_t(M) * size_t(c.nz) * size_t(c.nx) * 19u *
+    r.shell_bytes = r.nbands > 1 ? size_t(r.nbands) * 2u * size_t(M) * size_t(c.nz) * size_t(c.nx) * size_t(lat) *
                                        elem_size(c.storage)
                                  : 0;
     r.flag_stride = kFlagStride;
@@ -512,7 +524,8 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
     a.need_bias = ctx->force_wait_timeout ? (1 << 29) : 0;
     const bool walls = ctx->g.wall[0] || ctx->g.wall[1] || ctx->g.wall[2];
     const bool force = ctx->force != nullptr;
-    const size_t part = size_t(ctx->g.nx) * 19u * size_t(M) * size_t(ctx->g.nz) * elem_size(ctx->cfg.storage);
+    // one (band, first/last rows) slab of the band boundary copy: [x][q][row][z]
+    const size_t part = size_t(ctx->g.nx) * size_t(ctx->g.lat) * size_t(M) * size_t(ctx->g.nz) * elem_size(ctx->cfg.storage);
     const bool py = ctx->cfg.face[2] == LBM_PERIODIC;
     hipError_t e = hipSuccess;
     const long tix = timing_begin(ctx, M);

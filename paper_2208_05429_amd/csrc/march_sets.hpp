@@ -6,7 +6,7 @@
 
 namespace lbm {
 
-// D3Q15 / D3Q27 (one round): {M, TY, TZ, NT, pair-and-ring} for two and one
+// D3Q15 / D3Q27: {M, TY, TZ, NT, pair-and-ring} for two and one
 // merged steps, by set, storage and variant (0: the default, the fastest
 // measured at 256^3).  D3Q15 in FP32 has the pair-and-ring layout of
 // march_pr.hpp (an interior pair and a ring column per thread; even nz); in
@@ -31,5 +31,71 @@ constexpr SetShapes kSetShapes[] = {
 hipError_t launch_march_set(int lat, int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a,
                             hipStream_t s);
 int max_blocks_set(int lat, int storage, bool walls, bool force, const MarchPlan& p);
+hipError_t launch_march_q27(int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
+int max_blocks_q27(int storage, bool walls, bool force, const MarchPlan& p);
+
+// A plain-layout shape of a set.  Planes that run in rounds launch the build
+// with the band edge code (ROUNDS), the others the build without it.
+template <class LT, int S, int M, int TY, int TZ, int NT>
+struct SetShape {
+    static bool match(const MarchPlan& p)
+    {
+        return p.pr == 0 && p.pf == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+    }
+    template <bool R>
+    static hipError_t launch_r(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        if (force)
+            return walls ? launch_march_shape<S, M, TY, TZ, NT, true, true, R, LT>(p, a, s)
+                         : launch_march_shape<S, M, TY, TZ, NT, false, true, R, LT>(p, a, s);
+        return walls ? launch_march_shape<S, M, TY, TZ, NT, true, false, R, LT>(p, a, s)
+                     : launch_march_shape<S, M, TY, TZ, NT, false, false, R, LT>(p, a, s);
+    }
+    template <bool R>
+    static int max_blocks_r(bool walls, bool force)
+    {
+        if (force)
+            return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, true, R, LT>()
+                         : max_blocks_shape<S, M, TY, TZ, NT, false, true, R, LT>();
+        return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, false, R, LT>()
+                     : max_blocks_shape<S, M, TY, TZ, NT, false, false, R, LT>();
+    }
+    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        return p.nbands > 1 ? launch_r<true>(walls, force, p, a, s) : launch_r<false>(walls, force, p, a, s);
+    }
+    static int max_blocks(bool walls, bool force)
+    {
+        const int a = max_blocks_r<false>(walls, force), b = max_blocks_r<true>(walls, force);
+        return a < b ? a : b;
+    }
+};
+
+// A pair-and-ring shape of a set (march_pr.hpp: its band edge code is always
+// built in).
+template <class LT, int S, int M, int TY, int TZ>
+struct PRSetShape {
+    static constexpr int NT = TY * TZ / 2;
+    static bool match(const MarchPlan& p)
+    {
+        return p.pr == 1 && p.pf == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+    }
+    static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
+    {
+        if (force)
+            return walls ? launch_march_pr_shape<S, M, TY, TZ, true, true, 1, LT>(p, a, s)
+                         : launch_march_pr_shape<S, M, TY, TZ, false, true, 1, LT>(p, a, s);
+        return walls ? launch_march_pr_shape<S, M, TY, TZ, true, false, 1, LT>(p, a, s)
+                     : launch_march_pr_shape<S, M, TY, TZ, false, false, 1, LT>(p, a, s);
+    }
+    static int max_blocks(bool walls, bool force)
+    {
+        if (force)
+            return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, true, 1, LT>()
+                         : max_blocks_pr_shape<S, M, TY, TZ, false, true, 1, LT>();
+        return walls ? max_blocks_pr_shape<S, M, TY, TZ, true, false, 1, LT>()
+                     : max_blocks_pr_shape<S, M, TY, TZ, false, false, 1, LT>();
+    }
+};
 
 }  // namespace lbm

@@ -146,6 +146,9 @@ def test_velocity_sets_sizes_and_limits():
         assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q))[0] == capi.LBM_EUNSUPPORTED
         assert _status(_cfg(scheme=capi.LBM_SWAP3, velocities=q))[0] == capi.LBM_EUNSUPPORTED
         assert _status(_cfg(velocities=q, variant=4))[0] == capi.LBM_EUNSUPPORTED
-        # a plane of more tiles than co-resident workgroups would need rounds
-        assert _status(_cfg(shape=(8, 1024, 1024), velocities=q))[0] == capi.LBM_EUNSUPPORTED
+    # a plane of more tiles than co-resident workgroups runs in rounds: the
+    # work buffer then holds the band boundary rows of all Q directions
+    wb = {q: _status(_cfg(shape=(8, 1024, 1024), velocities=q)) for q in (15, 19, 27)}
+    assert all(v[0] == capi.LBM_OK for v in wb.values())
+    assert wb[15][2] < wb[19][2] < wb[27][2]
     assert _status(_cfg(velocities=20))[0] == capi.LBM_EINVAL

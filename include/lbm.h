@@ -97,8 +97,9 @@ typedef struct {
     int32_t use_force;  /* 1: a body-force density field F (3N, double for LBM_F64, float otherwise) */
     int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes */
     int32_t velocities; /* velocity set: 0 or 19 = D3Q19 (the paper's); 15 = D3Q15, 27 = D3Q27 (Sec. 4.1 names
-                           both as sets the two-step rule holds for): FP64 and FP32 storage, LBM_TWO_ARRAY,
-                           LBM_SWAP1 and LBM_SWAP2 (large planes in rounds), no adjoint or probes */
+                           both as sets the two-step rule holds for): every storage (16-bit: the default
+                           tiles), LBM_TWO_ARRAY, LBM_SWAP1 and LBM_SWAP2 (large planes in rounds), no adjoint
+                           or probes */
 } lbm_config;
 
 /* Bytes the caller must provide for the distribution buffer (Q*N values of

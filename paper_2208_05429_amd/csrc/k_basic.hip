@@ -235,6 +235,8 @@ static hipError_t init_set(int storage, const Geom& g, void* f, const double* rh
     switch (storage) {
     case ST_F64: return init_s<LT, ST_F64>(g, f, rho0, u0, s);
     case ST_F32: return init_s<LT, ST_F32>(g, f, rho0, u0, s);
+    case ST_F16: return init_s<LT, ST_F16>(g, f, rho0, u0, s);
+    case ST_BF16: return init_s<LT, ST_BF16>(g, f, rho0, u0, s);
     }
     return hipErrorInvalidValue;
 }
@@ -276,6 +278,11 @@ static hipError_t two_array_set(int storage, bool force, const Geom& g, const vo
         return force ? two_array_s<ST_F64, true, LT>(g, src, dst, F, s) : two_array_s<ST_F64, false, LT>(g, src, dst, F, s);
     case ST_F32:
         return force ? two_array_s<ST_F32, true, LT>(g, src, dst, F, s) : two_array_s<ST_F32, false, LT>(g, src, dst, F, s);
+    case ST_F16:
+        return force ? two_array_s<ST_F16, true, LT>(g, src, dst, F, s) : two_array_s<ST_F16, false, LT>(g, src, dst, F, s);
+    case ST_BF16:
+        return force ? two_array_s<ST_BF16, true, LT>(g, src, dst, F, s)
+                     : two_array_s<ST_BF16, false, LT>(g, src, dst, F, s);
     }
     return hipErrorInvalidValue;
 }
@@ -407,6 +414,12 @@ static hipError_t macro_set(int storage, bool force, const Geom& g, const void* 
     case ST_F32:
         return force ? macro_s<ST_F32, true, LT>(g, f, F, rho, u, unorm, partials, sums, s)
                      : macro_s<ST_F32, false, LT>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_F16:
+        return force ? macro_s<ST_F16, true, LT>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_F16, false, LT>(g, f, F, rho, u, unorm, partials, sums, s);
+    case ST_BF16:
+        return force ? macro_s<ST_BF16, true, LT>(g, f, F, rho, u, unorm, partials, sums, s)
+                     : macro_s<ST_BF16, false, LT>(g, f, F, rho, u, unorm, partials, sums, s);
     }
     return hipErrorInvalidValue;
 }

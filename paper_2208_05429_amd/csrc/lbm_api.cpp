@@ -294,8 +294,6 @@ lbm_status validate(const lbm_config* c, std::string* why)
     if (c->variant < 0) return fail(why, LBM_EINVAL, "variant must be >= 0");
     if (c->velocities != 0 && c->velocities != 15 && c->velocities != 19 && c->velocities != 27)
         return fail(why, LBM_EINVAL, "velocities must be 0 (D3Q19), 15, 19 or 27");
-    if (lat_of(*c) != 19 && c->storage != LBM_F64 && c->storage != LBM_F32)
-        return fail(why, LBM_EUNSUPPORTED, "D3Q15 and D3Q27 are built for FP64 and FP32 storage only");
     if (lat_of(*c) != 19 && c->scheme == LBM_SWAP3)
         return fail(why, LBM_EUNSUPPORTED, "three merged steps are built for D3Q19 only");
     return LBM_OK;

@@ -27,12 +27,23 @@ constexpr SetShapes kSetShapes[] = {
     {27, ST_F32, 0, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},  // two columns per thread
     {27, ST_F32, 1, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
     {27, ST_F64, 0, {2, 8, 24, 384, 0, 1}, {1, 10, 26, 384, 0, 1}},
+    // FP16/BF16 offset storage: the default tiles of FP32 (and the plain
+    // 16 x 64 tile that D3Q15 takes for odd nz)
+    {15, ST_F16, 0, {2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}},
+    {15, ST_F16, 1, {2, 16, 64, 512, 0, 1}, {1, 16, 64, 512, 0, 1}},
+    {15, ST_BF16, 0, {2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}},
+    {15, ST_BF16, 1, {2, 16, 64, 512, 0, 1}, {1, 16, 64, 512, 0, 1}},
+    {27, ST_F16, 0, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},
+    {27, ST_BF16, 0, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},
 };
 hipError_t launch_march_set(int lat, int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a,
                             hipStream_t s);
 int max_blocks_set(int lat, int storage, bool walls, bool force, const MarchPlan& p);
 hipError_t launch_march_q27(int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
 int max_blocks_q27(int storage, bool walls, bool force, const MarchPlan& p);
+hipError_t launch_march_set16(int lat, int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a,
+                              hipStream_t s);
+int max_blocks_set16(int lat, int storage, bool walls, bool force, const MarchPlan& p);
 
 // A plain-layout shape of a set.  Planes that run in rounds launch the build
 // with the band edge code (ROUNDS), the others the build without it.

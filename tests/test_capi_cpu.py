@@ -138,12 +138,13 @@ def test_three_merged_steps_are_built_for_fp32_only():
 
 def test_velocity_sets_sizes_and_limits():
     for q in (15, 19, 27):
-        for storage, s in ((capi.LBM_F64, 8), (capi.LBM_F32, 4)):
+        for storage, s in ((capi.LBM_F64, 8), (capi.LBM_F32, 4), (capi.LBM_F16_OFS, 2), (capi.LBM_BF16_OFS, 2)):
             st, fb, wb = _status(_cfg(storage=storage, velocities=q))
             assert st == capi.LBM_OK and fb == q * 32 ** 3 * s
     assert _status(_cfg(velocities=0))[1] == 19 * 32 ** 3 * 4  # 0 is D3Q19
     for q in (15, 27):
-        assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q))[0] == capi.LBM_EUNSUPPORTED
+        # 16-bit storage takes the default tiles only (and D3Q15's plain 16 x 64 as variant 1)
+        assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q, variant=2))[0] == capi.LBM_EUNSUPPORTED
         assert _status(_cfg(scheme=capi.LBM_SWAP3, velocities=q))[0] == capi.LBM_EUNSUPPORTED
         assert _status(_cfg(velocities=q, variant=4))[0] == capi.LBM_EUNSUPPORTED
     # a plane of more tiles than co-resident workgroups runs in rounds: the

@@ -143,6 +143,85 @@ def test_sets_in_rounds_match_two_array_bitwise(q, storage, case):
             assert torch.equal(raw, base), scheme
 
 
+# ---------------------------------------------------------------------------
+# FP16/BF16 offset storage.  From a state whose stored offsets are exact
+# 16-bit values, one pass computes in FP32 and rounds each offset once, so every
+# stored value lies within half a 16-bit ulp of the oracle of the set run from
+# the same decoded state (plus the FP32 arithmetic error).
+
+def _half_ulp(x, storage):
+    a = np.abs(x)
+    if storage == "f16":
+        return 0.5 * 2.0 ** (np.floor(np.log2(np.maximum(a, 2.0 ** -14))) - 10)
+    return 0.5 * 2.0 ** (np.floor(np.log2(np.maximum(a, 2.0 ** -126))) - 7)
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("scheme,steps", [("swap1", 1), ("swap2", 2), ("two_array", 1)])
+@pytest.mark.parametrize("force", [False, True])
+def test_sets_16bit_store_is_within_half_an_ulp_of_the_oracle(q, storage, scheme, steps, force):
+    from paper_2208_05429_amd.lattice import lattice_weights
+    shape = (12, 20, 70)  # even nz: D3Q15 takes the pair-and-ring layout
+    faces = (WALL, WALL, WALL, MOVING_WALL, WALL, WALL)
+    wall_u = (0.05, 0.0, 0.01)
+    rho0, u0 = _init(shape, 740)
+    F = wl.normal_field(shape, 1e-3, 741).astype(np.float32).astype(np.float64) if force else None
+    print(f"[gpu] D3Q{q} one {storage} store, {scheme}, force {force}", flush=True)
+    lat = Lattice(shape, 0.7, storage, scheme, [NAMES[f] for f in faces], wall_u,
+                  None if F is None else torch.as_tensor(F), torch.as_tensor(rho0), torch.as_tensor(u0), velocities=q)
+    f0 = lat.distributions()  # the decoded 16-bit state: exact in FP64
+    lat.step(steps)
+    torch.cuda.synchronize()
+    w = lattice_weights(q)[:, None, None, None]
+    g_gpu = lat.distributions() - w
+    lat.close()
+    o = OracleQ(shape, 0.7, q, faces=faces, wall_u=wall_u)
+    g_ref = o.run(np.ascontiguousarray(f0), steps, F) - w
+    err = np.abs(g_gpu - g_ref)
+    bound = _half_ulp(np.maximum(np.abs(g_ref), np.abs(g_gpu)), storage) * (1 + 1e-3) + 2e-7
+    worst = float((err / bound).max())
+    print(f"D3Q{q} {storage} {scheme} force {force}: max err/bound = {worst:.3f}")
+    assert worst <= 1.0, worst
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage,case", [("f16", 0), ("f16", 1), ("bf16", 2)])
+def test_sets_16bit_in_rounds_in_place_matches_out_of_place(q, storage, case):
+    # the merged pass rounds to 16 bits once per two steps, so the reference is
+    # the same pass out of place (its band edges read the untouched source)
+    shape, faces, wall_u = BANDED[case]
+    rho0, u0 = _init(shape, 750 + case)
+    print(f"[gpu] rounds D3Q{q} {storage} {shape}", flush=True)
+    lat = Lattice(shape, 0.6, storage, "swap2", [NAMES[f] for f in faces], wall_u, rho0=torch.as_tensor(rho0),
+                  u0=torch.as_tensor(u0), velocities=q)
+    a, b = torch.empty_like(lat.f), torch.empty_like(lat.f)
+    lat.step_into(lat.f, a, 2)
+    lat.step_into(a, b, 2)
+    lat.step(4)
+    s = lat.sums()
+    assert np.isfinite(s).all()
+    assert torch.equal(lat.f.view(torch.int16), b.view(torch.int16))
+    lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_d3q15_16bit_layouts_agree_bitwise(storage):
+    # the pair-and-ring and the plain 16 x 64 layouts run the same per-cell
+    # arithmetic on the same inputs: their 16-bit stores agree to the bit
+    shape, faces, wall_u = CASES[6]
+    rho0, u0 = _init(shape, 760)
+    states = []
+    for variant in (0, 1):
+        lat = Lattice(shape, 0.6, storage, "swap2", [NAMES[f] for f in faces], wall_u, rho0=torch.as_tensor(rho0),
+                      u0=torch.as_tensor(u0), variant=variant, velocities=15)
+        lat.step(5)
+        torch.cuda.synchronize()
+        states.append(lat.f.view(torch.int16).clone())
+        lat.close()
+    assert torch.equal(states[0], states[1])
+
+
 def test_sets_run_without_allocation_too():
     # the allocation-free entry point takes the same configurations
     shape = (20, 24, 30)

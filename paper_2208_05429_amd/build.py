@@ -31,10 +31,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           f"-I{os.path.join(os.path.dirname(HERE), 'include')}"]
 
 
-# the sources the marching kernels and their launch configuration are built
-# from (the kernels' code and the host's choice of shape, segments and grid)
+# the sources the FP32 D3Q19 marching kernels and their launch configuration
+# are built from (the kernels' code and the host's choice of shape, segments
+# and grid); stored counters of those kernels carry this digest
 MARCH_SOURCES = ("d3q19.hpp", "lattices.hpp", "lbm_internal.hpp", "march.hpp", "march_pr.hpp", "march_dispatch.hpp",
-                 "march_sets.hpp", "march_f32.hip", "march_f16.hip", "march_bf16.hip", "march_f64.hip", "lbm_api.cpp")
+                 "march_f32.hip", "lbm_api.cpp")
 
 
 def source_digest(names=MARCH_SOURCES) -> str:

@@ -93,6 +93,12 @@ def lib():
             fn.restype = ctypes.c_int32
         L.orq_run.argtypes = [cq, d, d, d, ctypes.c_int64]
         L.orq_run.restype = ctypes.c_int32
+        L.orq_loss.argtypes = [cq, d, d, d]
+        L.orq_loss.restype = ctypes.c_double
+        L.orq_loss_seed.argtypes = [cq, d, d, d, d, d]
+        L.orq_loss_seed.restype = ctypes.c_int32
+        L.orq_adjoint_step.argtypes = [cq, d, d, d, d, d]
+        L.orq_adjoint_step.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -254,7 +260,8 @@ def tables_q(q):
 
 class OracleQ(Oracle):
     """Oracle over velocity set ``q`` (15, 19 or 27): init, run, collide,
-    stream, macro and sums as ``Oracle`` (no adjoint)."""
+    stream, macro, sums and the discrete adjoint (loss, seed, one reverse
+    step; loss_and_grad as ``Oracle``)."""
 
     def __init__(self, shape, tau, q, faces=(PERIODIC,) * 6, wall_u=(0.0, 0.0, 0.0)):
         self.shape = tuple(int(s) for s in shape)
@@ -305,5 +312,28 @@ class OracleQ(Oracle):
         _chk(lib().orq_sums(ctypes.byref(self.cfg), _p(np.ascontiguousarray(f, np.float64)), _p(out)), "sums")
         return out
 
+    def loss(self, f, utarget, F=None):
+        Fa = None if F is None else np.ascontiguousarray(F, np.float64)
+        return lib().orq_loss(ctypes.byref(self.cfg), _p(Fa), _p(np.ascontiguousarray(f, np.float64)),
+                              _p(np.ascontiguousarray(utarget, np.float64)))
+
+    def loss_seed(self, f, utarget, F=None):
+        lam = np.empty(self._fshape(self.Q))
+        gF = np.zeros(self._fshape(3))
+        Fa = None if F is None else np.ascontiguousarray(F, np.float64)
+        _chk(lib().orq_loss_seed(ctypes.byref(self.cfg), _p(Fa), _p(np.ascontiguousarray(f, np.float64)),
+                                 _p(np.ascontiguousarray(utarget, np.float64)), _p(lam), _p(gF)), "loss_seed")
+        return lam, gF
+
+    def adjoint_step(self, f_t, lam_next, F=None, gradF=None):
+        """Returns (lambda_t, gradF + this step's contribution)."""
+        lam = np.array(lam_next, np.float64, order="C", copy=True)
+        tmp = np.empty_like(lam)
+        g = np.zeros(self._fshape(3)) if gradF is None else np.array(gradF, np.float64, order="C", copy=True)
+        Fa = None if F is None else np.ascontiguousarray(F, np.float64)
+        _chk(lib().orq_adjoint_step(ctypes.byref(self.cfg), _p(Fa), _p(np.ascontiguousarray(f_t, np.float64)),
+                                    _p(lam), _p(tmp), _p(g)), "adjoint_step")
+        return lam, g
+
     def collide_adjoint_cell(self, *a, **k):
-        raise NotImplementedError("the generic-lattice oracle has no adjoint")
+        raise NotImplementedError("the generic-lattice oracle's adjoint works on whole lattices")

@@ -286,3 +286,134 @@ int32_t orq_sums(const orq_cfg* g, const double* f, double* out)
     for (int k = 0; k < 4; ++k) out[k] = s[k];
     return 0;
 }
+
+/* ---- discrete adjoint of one step f_{t+1} = S(C(f_t; F)) over the set ----
+ *
+ * For the loss of the final velocity L = sum_x |u(x,T) - u*(x)|^2, written
+ * from the chain rule with rho = sum f, u = (sum c f + F/2)/rho, so that
+ * d rho / d f_j = 1, d u / d f_j = (c_j - u)/rho and d u / d F = 1/(2 rho):
+ *   seed      lambda_q(T) = 2 (u - u*) . (c_q - u)/rho,  dL/dF += (u - u*)/rho
+ *   stream^T  the push moves f*_q(x) to x + c_q, or to slot opp(q) of x where
+ *             the link leaves through a wall (minus a constant), so
+ *             mu_q(x) = lambda_q(x + c_q, t+1) or lambda_opp(q)(x, t+1)
+ *   collide^T f*_q = (1 - omega) f_q + omega feq_q(rho, u) + S_q(u, F), with
+ *             d feq_q / d rho = feq_q / rho,
+ *             d feq_q / d u = w_q rho (3 c_q + 9 (c_q.u) c_q - 3 u),
+ *             d S_q / d u  = (1 - omega/2) w_q (9 (c_q.F) c_q - 3 F),
+ *             d S_q / d F  = (1 - omega/2) w_q (3 (c_q - u) + 9 (c_q.u) c_q):
+ *     a_rho = sum_q mu_q omega feq_q / rho
+ *     a_u   = sum_q mu_q [omega d feq_q / d u + d S_q / d u]
+ *     lambda_j(t) = (1 - omega) mu_j + a_rho + a_u . (c_j - u)/rho
+ *     dL/dF += sum_q mu_q d S_q / d F + a_u / (2 rho)
+ */
+
+static void cell_state(const lattice_t* L, const double* f, size_t N, size_t i, const double* F, double* fc,
+                       double* Fc, double* rho, double u[3])
+{
+    for (int q = 0; q < L->Q; ++q) fc[q] = f[q * N + i];
+    Fc[0] = Fc[1] = Fc[2] = 0.0;
+    if (F)
+        for (int a = 0; a < 3; ++a) Fc[a] = F[a * N + i];
+    moments(L, fc, F ? Fc : NULL, rho, u);
+}
+
+double orq_loss(const orq_cfg* g, const double* F, const double* f, const double* utarget)
+{
+    lattice_t L;
+    if (orq_check(g)) return NAN;
+    make_lattice(g->q, &L);
+    size_t N = ncell(g);
+    double s = 0.0;
+    for (size_t i = 0; i < N; ++i) {
+        double fc[QMAX], Fc[3], rho, u[3];
+        cell_state(&L, f, N, i, F, fc, Fc, &rho, u);
+        for (int a = 0; a < 3; ++a) {
+            double d = u[a] - utarget[a * N + i];
+            s += d * d;
+        }
+    }
+    return s;
+}
+
+/* lambda := dL/df of the final state (Q N values); gF += the direct dL/dF */
+int32_t orq_loss_seed(const orq_cfg* g, const double* F, const double* f, const double* utarget, double* lambda,
+                      double* gF)
+{
+    lattice_t L;
+    if (orq_check(g)) return -1;
+    make_lattice(g->q, &L);
+    size_t N = ncell(g);
+    for (size_t i = 0; i < N; ++i) {
+        double fc[QMAX], Fc[3], rho, u[3], d[3];
+        cell_state(&L, f, N, i, F, fc, Fc, &rho, u);
+        for (int a = 0; a < 3; ++a) d[a] = u[a] - utarget[a * N + i];
+        for (int q = 0; q < L.Q; ++q) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a) s += d[a] * (L.c[q][a] - u[a]);
+            lambda[q * N + i] = 2.0 * s / rho;
+        }
+        if (gF)
+            for (int a = 0; a < 3; ++a) gF[a * N + i] += d[a] / rho;
+    }
+    return 0;
+}
+
+/* One reverse step: lambda holds lambda_{t+1} on entry and lambda_t on exit;
+ * f_t is the state before the forward step; mu is Q N scratch; gF += this
+ * step's dL/dF (may be NULL). */
+int32_t orq_adjoint_step(const orq_cfg* g, const double* F, const double* f_t, double* lambda, double* mu,
+                         double* gF)
+{
+    lattice_t L;
+    if (orq_check(g)) return -1;
+    make_lattice(g->q, &L);
+    size_t N = ncell(g);
+    int n[3] = {g->nx, g->ny, g->nz};
+    const double omega = 1.0 / g->tau, kf = 1.0 - 0.5 * omega;
+    /* stream^T */
+    for (int x = 0; x < g->nx; ++x)
+        for (int y = 0; y < g->ny; ++y)
+            for (int z = 0; z < g->nz; ++z) {
+                size_t i = ((size_t)x * g->ny + y) * g->nz + z;
+                for (int q = 0; q < L.Q; ++q) {
+                    int p[3] = {x + L.c[q][0], y + L.c[q][1], z + L.c[q][2]};
+                    int inside = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (p[a] >= 0 && p[a] < n[a]) continue;
+                        if (g->face[2 * a + (p[a] >= n[a])] == 0)
+                            p[a] = (p[a] + n[a]) % n[a];
+                        else
+                            inside = 0;
+                    }
+                    mu[q * N + i] = inside ? lambda[q * N + ((size_t)p[0] * g->ny + p[1]) * g->nz + p[2]]
+                                           : lambda[L.opp[q] * N + i];
+                }
+            }
+    /* collide^T, cell by cell */
+    for (size_t i = 0; i < N; ++i) {
+        double fc[QMAX], Fc[3], rho, u[3], feq[QMAX];
+        cell_state(&L, f_t, N, i, F, fc, Fc, &rho, u);
+        equilibrium(&L, rho, u, feq);
+        double a_rho = 0.0, a_u[3] = {0.0, 0.0, 0.0}, dF[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < L.Q; ++q) {
+            const double m = mu[q * N + i];
+            const double cu = L.c[q][0] * u[0] + L.c[q][1] * u[1] + L.c[q][2] * u[2];
+            const double cF = L.c[q][0] * Fc[0] + L.c[q][1] * Fc[1] + L.c[q][2] * Fc[2];
+            a_rho += m * omega * feq[q] / rho;
+            for (int a = 0; a < 3; ++a) {
+                const double dfeq = L.w[q] * rho * (3.0 * L.c[q][a] + 9.0 * cu * L.c[q][a] - 3.0 * u[a]);
+                const double dS = F ? kf * L.w[q] * (9.0 * cF * L.c[q][a] - 3.0 * Fc[a]) : 0.0;
+                a_u[a] += m * (omega * dfeq + dS);
+                dF[a] += m * kf * L.w[q] * (3.0 * (L.c[q][a] - u[a]) + 9.0 * cu * L.c[q][a]);
+            }
+        }
+        for (int j = 0; j < L.Q; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a) s += a_u[a] * (L.c[j][a] - u[a]);
+            lambda[j * N + i] = (1.0 - omega) * mu[j * N + i] + a_rho + s / rho;
+        }
+        if (gF)
+            for (int a = 0; a < 3; ++a) gF[a * N + i] += dF[a] + a_u[a] / (2.0 * rho);
+    }
+    return 0;
+}

@@ -15,6 +15,11 @@ of the paper states that its two-step rule holds for D3Q15, D3Q19 and D3Q27.
   nu k^2 with nu = (tau - 1/2)/3 along every axis; Poiseuille flow has the
   exact curvature -g/(2 nu), and the exact halfway profile at
   tau = 1/2 + sqrt(3/16); Couette flow under a moving wall is linear.
+* Discrete adjoint, per set: the seed is the gradient of the loss and one
+  reverse step the gradient of <lambda, step(f, F)> in f and in F (central
+  differences of the forward oracle, on walls, a lid and periodic faces), and
+  several steps end to end match differences of the whole run; the D3Q19
+  case equals the separate D3Q19 oracle's adjoint.
 """
 import math
 
@@ -183,3 +188,106 @@ def test_poiseuille_profile_exact_at_magic_tau(q):
     y = np.arange(H, dtype=np.float64)
     exact = g / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
     assert np.abs(u[0, 0, :, 0] - exact).max() <= 1e-9 * exact.max()
+
+
+# ---------------------------------------------------------------------------
+# discrete adjoint, pinned by central differences of the forward oracle
+
+ADJ_FACES = (WALL, MOVING_WALL, PERIODIC, PERIODIC, WALL, WALL)
+ADJ_WALL_U = (0.0, 0.02, 0.01)
+
+
+def _adj_problem(q, shape=(5, 6, 7), seed=900):
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, seed)
+    o = OracleQ(shape, 0.7, q, faces=ADJ_FACES, wall_u=ADJ_WALL_U)
+    f = o.init(wl.random_density(shape, 0.01, seed + 1), u0)
+    F = wl.normal_field(shape, 1e-3, seed + 2)
+    return o, f, F
+
+
+def _entries(rng, shape, n):
+    # random entries, and the cells next to each wall face and the lid
+    idx = [tuple(int(rng.integers(0, s)) for s in shape) for _ in range(n)]
+    idx += [(0, 2, 0), (shape[0] - 1, 3, shape[2] - 1), (2, 0, 3), (1, shape[1] - 1, 0)]
+    return idx
+
+
+@pytest.mark.parametrize("q", SETS)
+def test_adjoint_seed_is_the_gradient_of_the_loss(q):
+    o, f, F = _adj_problem(q)
+    ut = wl.normal_field(o.shape, 1e-2, 910)
+    lam, gF = o.loss_seed(f, ut, F)
+    rng = np.random.default_rng(911)
+    eps = 1e-6
+    for x, y, z in _entries(rng, o.shape, 8):
+        p = int(rng.integers(0, q))
+        fp, fm = f.copy(), f.copy()
+        fp[p, x, y, z] += eps
+        fm[p, x, y, z] -= eps
+        fd = (o.loss(fp, ut, F) - o.loss(fm, ut, F)) / (2 * eps)
+        assert abs(fd - lam[p, x, y, z]) <= 1e-7 * max(1.0, abs(fd)), (p, x, y, z, fd, lam[p, x, y, z])
+        a = int(rng.integers(0, 3))
+        Fp, Fm = F.copy(), F.copy()
+        Fp[a, x, y, z] += eps
+        Fm[a, x, y, z] -= eps
+        fd = (o.loss(f, ut, Fp) - o.loss(f, ut, Fm)) / (2 * eps)
+        assert abs(fd - gF[a, x, y, z]) <= 1e-7 * max(1.0, abs(fd)), (a, x, y, z, fd, gF[a, x, y, z])
+
+
+@pytest.mark.parametrize("q", SETS)
+def test_adjoint_step_is_the_gradient_of_one_step(q):
+    o, f, F = _adj_problem(q)
+    lam_next = wl.normal_field(o.shape, 1.0, 920, comps=q)
+    lam, gF = o.adjoint_step(f, lam_next, F)
+
+    def phi(ff, FF):
+        return float(np.sum(lam_next * o.run(ff, 1, FF)))
+
+    rng = np.random.default_rng(921)
+    eps = 1e-6
+    for x, y, z in _entries(rng, o.shape, 10):
+        p = int(rng.integers(0, q))
+        fp, fm = f.copy(), f.copy()
+        fp[p, x, y, z] += eps
+        fm[p, x, y, z] -= eps
+        fd = (phi(fp, F) - phi(fm, F)) / (2 * eps)
+        assert abs(fd - lam[p, x, y, z]) <= 1e-7 * max(1.0, abs(fd)), (p, x, y, z, fd, lam[p, x, y, z])
+        a = int(rng.integers(0, 3))
+        Fp, Fm = F.copy(), F.copy()
+        Fp[a, x, y, z] += eps
+        Fm[a, x, y, z] -= eps
+        fd = (phi(f, Fp) - phi(f, Fm)) / (2 * eps)
+        assert abs(fd - gF[a, x, y, z]) <= 1e-7 * max(1.0, abs(fd)), (a, x, y, z, fd, gF[a, x, y, z])
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_adjoint_over_several_steps_matches_differences_of_the_run(q):
+    o, f, F = _adj_problem(q, shape=(4, 5, 6), seed=930)
+    ut = wl.normal_field(o.shape, 1e-2, 931)
+    steps = 4
+    L, g = o.loss_and_grad(f, F, ut, steps)
+    rng = np.random.default_rng(932)
+    eps = 1e-6
+    for _ in range(8):
+        a, x, y, z = (int(rng.integers(0, n)) for n in (3,) + o.shape)
+        Fp, Fm = F.copy(), F.copy()
+        Fp[a, x, y, z] += eps
+        Fm[a, x, y, z] -= eps
+        fd = (o.loss(o.run(f, steps, Fp), ut, Fp) - o.loss(o.run(f, steps, Fm), ut, Fm)) / (2 * eps)
+        assert abs(fd - g[a, x, y, z]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (a, x, y, z, fd, g[a, x, y, z])
+
+
+def test_d3q19_adjoint_equals_the_d3q19_oracle_adjoint():
+    o, f, F = _adj_problem(19)
+    ref = Oracle(o.shape, 0.7, faces=ADJ_FACES, wall_u=ADJ_WALL_U)
+    lam_next = wl.normal_field(o.shape, 1.0, 940, comps=19)
+    ut = wl.normal_field(o.shape, 1e-2, 941)
+    a, ga = o.adjoint_step(f, lam_next, F)
+    b, gb = ref.adjoint_step(f, lam_next, F)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * np.abs(b).max())
+    np.testing.assert_allclose(ga, gb, rtol=0, atol=1e-13 * np.abs(gb).max())
+    a, ga = o.loss_seed(f, ut, F)
+    b, gb = ref.loss_seed(f, ut, F)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-14 * np.abs(b).max())
+    np.testing.assert_allclose(ga, gb, rtol=0, atol=1e-14 * np.abs(gb).max())

@@ -9,7 +9,8 @@ each checkpoint interval in reverse: recompute the states the reverse steps star
 out of place, so no state is ever copied), and run the adjoint backwards
 (lbm_step_adjoint), accumulating dL/dF.  With spec["merged"] the reverse
 steps go two at a time (the adjoint of the merged pass, f_{t+1} recomputed on
-chip), so only every other state is needed.
+chip), so only every other state is needed (D3Q19; the D3Q15 and D3Q27
+sets reverse one step per call).
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ class ForceAdjoint(torch.autograd.Function):
         steps, k = int(spec["steps"]), int(spec["checkpoint"])
         lat = Lattice(shape, spec["tau"], storage, spec.get("scheme", "swap2"), spec["faces"],
                       spec.get("wall_u", (0.0, 0.0, 0.0)), force=F.detach(),
-                      f=torch.empty(f0.shape, dtype=f0.dtype, device=f0.device))
+                      f=torch.empty(f0.shape, dtype=f0.dtype, device=f0.device), velocities=f0.shape[0])
         ckpts = [f0.detach().clone(memory_format=torch.contiguous_format)]
         t = 0
         while t < steps:
@@ -58,7 +59,7 @@ class ForceAdjoint(torch.autograd.Function):
         shape = lat.shape
         rdt = real_dtype(lat.storage)
         dev = lat.device
-        lam = torch.empty((19,) + shape, dtype=rdt, device=dev)
+        lam = torch.empty((lat.Q,) + shape, dtype=rdt, device=dev)
         lam2 = torch.empty_like(lam)
         gF = torch.zeros((3,) + shape, dtype=rdt, device=dev)
         gu = grad_u.to(device=dev, dtype=rdt).contiguous()

@@ -14,7 +14,7 @@
 namespace lbm {
 
 // lambda := dL/df from dL/du of the state f; gradF += dL/du / (2 rho)
-template <int S, bool FORCE>
+template <int S, bool FORCE, class LT = D3Q19>
 __global__ __launch_bounds__(256) void k_macro_adjoint(Geom g, const typename Codec<S>::T* __restrict__ f,
                                                        const typename Codec<S>::R* __restrict__ F,
                                                        const typename Codec<S>::R* __restrict__ gu,
@@ -25,25 +25,26 @@ __global__ __launch_bounds__(256) void k_macro_adjoint(Geom g, const typename Co
     using R = typename Cd::R;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= g.N) return;
-    R v[Q];
+    constexpr int QL = LT::Q;
+    R v[QL];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(f[q * g.N + i]);
+    for (int q = 0; q < QL; ++q) v[q] = Cd::dec(f[q * g.N + i]);
     R Fx = R(0), Fy = R(0), Fz = R(0);
     if constexpr (FORCE) {
         Fx = F[i];
         Fy = F[g.N + i];
         Fz = F[2 * g.N + i];
     }
-    const Moments<R> m = moments<R, FORCE>(v, Fx, Fy, Fz);
+    const Moments<R> m = moments_l<R, FORCE, LT>(v, Fx, Fy, Fz);
     const R inv = R(1) / m.rho;
     const R gx = gu[i], gy = gu[g.N + i], gz = gu[2 * g.N + i];
     const R gdu = gx * m.ux + gy * m.uy + gz * m.uz;
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, QL>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         R cg = R(0);
-        if constexpr (cxq(q) != 0) cg += R(cxq(q)) * gx;
-        if constexpr (cyq(q) != 0) cg += R(cyq(q)) * gy;
-        if constexpr (czq(q) != 0) cg += R(czq(q)) * gz;
+        if constexpr (LT::cx(q) != 0) cg += R(LT::cx(q)) * gx;
+        if constexpr (LT::cy(q) != 0) cg += R(LT::cy(q)) * gy;
+        if constexpr (LT::cz(q) != 0) cg += R(LT::cz(q)) * gz;
         lam[q * g.N + i] = (cg - gdu) * inv;
     });
     if (gF) {
@@ -56,14 +57,14 @@ __global__ __launch_bounds__(256) void k_macro_adjoint(Geom g, const typename Co
 
 // mu_q(x): lambda_q at the target of the link (x, q), or lambda_opp(q)(x) when
 // the link leaves through a wall face
-template <class R, bool WALLS>
+template <class R, bool WALLS, class LT = D3Q19>
 __device__ __forceinline__ void stream_adjoint_gather(const Geom& g, const R* __restrict__ lin, int x, int y, int z,
-                                                      long long i, R (&mu)[Q])
+                                                      long long i, R (&mu)[LT::Q])
 {
     const int n[3] = {g.nx, g.ny, g.nz};
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        const int c[3] = {cxq(q), cyq(q), czq(q)};
+        const int c[3] = {LT::cx(q), LT::cy(q), LT::cz(q)};
         int p[3] = {x + c[0], y + c[1], z + c[2]};
         bool out = false;
 #pragma unroll
@@ -75,14 +76,14 @@ __device__ __forceinline__ void stream_adjoint_gather(const Geom& g, const R* __
                 p[ax] = p[ax] < 0 ? p[ax] + n[ax] : p[ax] - n[ax];
         }
         if (WALLS && out)
-            mu[q] = lin[oppq(q) * g.N + i];
+            mu[q] = lin[LT::opp(q) * g.N + i];
         else
             mu[q] = lin[q * g.N + ((long long)p[0] * g.ny + p[1]) * g.nz + p[2]];
     });
 }
 
 // one reverse step: lam_out = adjoint of one step at f_t applied to lam_in
-template <int S, bool WALLS, bool FORCE>
+template <int S, bool WALLS, bool FORCE, class LT = D3Q19>
 __global__ __launch_bounds__(256) void k_adjoint1(Geom g, const typename Codec<S>::T* __restrict__ ft,
                                                   const typename Codec<S>::R* __restrict__ F,
                                                   const typename Codec<S>::R* __restrict__ lin,
@@ -96,10 +97,11 @@ __global__ __launch_bounds__(256) void k_adjoint1(Geom g, const typename Codec<S
     const int z = int(i % g.nz);
     const long long r = i / g.nz;
     const int y = int(r % g.ny), x = int(r / g.ny);
-    R mu[Q], v[Q], lam[Q];
-    stream_adjoint_gather<R, WALLS>(g, lin, x, y, z, i, mu);
+    constexpr int QL = LT::Q;
+    R mu[QL], v[QL], lam[QL];
+    stream_adjoint_gather<R, WALLS, LT>(g, lin, x, y, z, i, mu);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = Cd::dec(ft[q * g.N + i]);
+    for (int q = 0; q < QL; ++q) v[q] = Cd::dec(ft[q * g.N + i]);
     R Fx = R(0), Fy = R(0), Fz = R(0);
     if constexpr (FORCE) {
         Fx = F[i];
@@ -107,9 +109,9 @@ __global__ __launch_bounds__(256) void k_adjoint1(Geom g, const typename Codec<S
         Fz = F[2 * g.N + i];
     }
     R gx, gy, gz;
-    collide_adjoint<R, FORCE>(v, mu, R(g.omega), Fx, Fy, Fz, lam, gx, gy, gz);
+    collide_adjoint<R, FORCE, LT>(v, mu, R(g.omega), Fx, Fy, Fz, lam, gx, gy, gz);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lout[q * g.N + i] = lam[q];
+    for (int q = 0; q < QL; ++q) lout[q * g.N + i] = lam[q];
     if (FORCE && gF) {
         gF[i] += gx;
         gF[g.N + i] += gy;
@@ -117,21 +119,44 @@ __global__ __launch_bounds__(256) void k_adjoint1(Geom g, const typename Codec<S
     }
 }
 
-template <int S, bool FORCE>
+template <int S, bool FORCE, class LT = D3Q19>
 static hipError_t macro_adjoint_s(const Geom& g, const void* f, const void* F, const void* gu, void* lam, void* gF,
                                   hipStream_t s)
 {
     using Cd = Codec<S>;
     using R = typename Cd::R;
-    hipLaunchKernelGGL((k_macro_adjoint<S, FORCE>), dim3(unsigned((g.N + 255) / 256)), dim3(256), 0, s, g,
+    hipLaunchKernelGGL((k_macro_adjoint<S, FORCE, LT>), dim3(unsigned((g.N + 255) / 256)), dim3(256), 0, s, g,
                        static_cast<const typename Cd::T*>(f), static_cast<const R*>(F), static_cast<const R*>(gu),
                        static_cast<R*>(lam), static_cast<R*>(gF));
     return hipGetLastError();
 }
 
+template <class LT>
+static hipError_t macro_adjoint_set(int storage, bool force, const Geom& g, const void* f, const void* F,
+                                    const void* grad_u, void* lambda, void* grad_force, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64:
+        return force ? macro_adjoint_s<ST_F64, true, LT>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_F64, false, LT>(g, f, F, grad_u, lambda, grad_force, s);
+    case ST_F32:
+        return force ? macro_adjoint_s<ST_F32, true, LT>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_F32, false, LT>(g, f, F, grad_u, lambda, grad_force, s);
+    case ST_F16:
+        return force ? macro_adjoint_s<ST_F16, true, LT>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_F16, false, LT>(g, f, F, grad_u, lambda, grad_force, s);
+    case ST_BF16:
+        return force ? macro_adjoint_s<ST_BF16, true, LT>(g, f, F, grad_u, lambda, grad_force, s)
+                     : macro_adjoint_s<ST_BF16, false, LT>(g, f, F, grad_u, lambda, grad_force, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const void* f, const void* F,
                                 const void* grad_u, void* lambda, void* grad_force, hipStream_t s)
 {
+    if (g.lat == 15) return macro_adjoint_set<D3Q15>(storage, force, g, f, F, grad_u, lambda, grad_force, s);
+    if (g.lat == 27) return macro_adjoint_set<D3Q27>(storage, force, g, f, F, grad_u, lambda, grad_force, s);
     switch (storage) {
     case ST_F64:
         return force ? macro_adjoint_s<ST_F64, true>(g, f, F, grad_u, lambda, grad_force, s)
@@ -149,7 +174,7 @@ hipError_t launch_macro_adjoint(int storage, bool force, const Geom& g, const vo
     return hipErrorInvalidValue;
 }
 
-template <int S, bool FORCE>
+template <int S, bool FORCE, class LT = D3Q19>
 static hipError_t adjoint1_s(const Geom& g, const void* ft, const void* F, const void* lin, void* lout, void* gF,
                              hipStream_t s)
 {
@@ -163,15 +188,41 @@ static hipError_t adjoint1_s(const Geom& g, const void* ft, const void* F, const
     auto gp = static_cast<R*>(gF);
     const dim3 grid(unsigned((g.N + 255) / 256));
     if (walls)
-        hipLaunchKernelGGL((k_adjoint1<S, true, FORCE>), grid, dim3(256), 0, s, g, fp, Fp, li, lo, gp);
+        hipLaunchKernelGGL((k_adjoint1<S, true, FORCE, LT>), grid, dim3(256), 0, s, g, fp, Fp, li, lo, gp);
     else
-        hipLaunchKernelGGL((k_adjoint1<S, false, FORCE>), grid, dim3(256), 0, s, g, fp, Fp, li, lo, gp);
+        hipLaunchKernelGGL((k_adjoint1<S, false, FORCE, LT>), grid, dim3(256), 0, s, g, fp, Fp, li, lo, gp);
     return hipGetLastError();
+}
+
+template <class LT>
+static hipError_t adjoint1_set(int storage, bool force, const Geom& g, const void* f_t, const void* F,
+                               const void* lam_in, void* lam_out, void* grad_force, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64:
+        return force ? adjoint1_s<ST_F64, true, LT>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_F64, false, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F32:
+        return force ? adjoint1_s<ST_F32, true, LT>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_F32, false, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F16:
+        return force ? adjoint1_s<ST_F16, true, LT>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_F16, false, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_BF16:
+        return force ? adjoint1_s<ST_BF16, true, LT>(g, f_t, F, lam_in, lam_out, grad_force, s)
+                     : adjoint1_s<ST_BF16, false, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, const void* f_t, const void* F,
                                const void* lam_in, void* lam_out, void* grad_force, hipStream_t s)
 {
+    if (g.lat != 19) {  // one reverse step per call (the merged two-step adjoint is built for D3Q19)
+        if (k != 1) return hipErrorInvalidValue;
+        return g.lat == 15 ? adjoint1_set<D3Q15>(storage, force, g, f_t, F, lam_in, lam_out, grad_force, s)
+                           : adjoint1_set<D3Q27>(storage, force, g, f_t, F, lam_in, lam_out, grad_force, s);
+    }
     if (k == 2) return launch_step_adjoint2(storage, g, f_t, force ? F : nullptr, lam_in, lam_out, grad_force, s);
     if (k != 1) return hipErrorInvalidValue;
     switch (storage) {

@@ -775,7 +775,6 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
 {
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
     ctx->err.clear();
-    if (ctx->g.lat != 19) return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for D3Q19 only");
     if (!f_dev || !grad_u_dev || !lambda_dev) return fail(&ctx->err, LBM_EINVAL, "f, grad_u and lambda are required");
     if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
     return device_err(ctx,
@@ -789,8 +788,9 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
 {
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
     ctx->err.clear();
-    if (ctx->g.lat != 19) return fail(&ctx->err, LBM_EUNSUPPORTED, "the adjoint is built for D3Q19 only");
     if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
+    if (ctx->g.lat != 19 && k != 1)
+        return fail(&ctx->err, LBM_EUNSUPPORTED, "the merged (k = 2) adjoint is built for D3Q19 only");
     if (!f_t_dev || !lambda_in_dev || !lambda_out_dev)
         return fail(&ctx->err, LBM_EINVAL, "f_t, lambda_in and lambda_out are required");
     if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");
@@ -798,7 +798,7 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
         (grad_force_dev && !aligned(grad_force_dev)))
         return fail(&ctx->err, LBM_EINVAL, "device buffers must be 256-byte aligned");
     // lambda_out is written while lambda_in is still read by other workgroups
-    const size_t lam_bytes = size_t(19) * size_t(ctx->g.N) * real_size(ctx->cfg.storage);
+    const size_t lam_bytes = size_t(ctx->g.lat) * size_t(ctx->g.N) * real_size(ctx->cfg.storage);
     const char* li = static_cast<const char*>(lambda_in_dev);
     const char* lo = static_cast<const char*>(lambda_out_dev);
     if (li < lo + lam_bytes && lo < li + lam_bytes)

@@ -35,7 +35,7 @@ class Lattice:
     faces    6 codes for -x,+x,-y,+y,-z,+z ('periodic' | 'wall' | 'moving')
     force    optional torch tensor (3, nx, ny, nz) of real_dtype(storage)
     rho0/u0  optional float64 tensors (nx,ny,nz) / (3,nx,ny,nz); None = 1 / 0
-    velocities  19 (D3Q19), 15 or 27 (the other cubic sets; FP64/FP32 storage)
+    velocities  19 (D3Q19), 15 or 27 (the other cubic sets)
     """
 
     def __init__(self, shape, tau, storage="f32", scheme="swap2", faces=("periodic",) * 6,

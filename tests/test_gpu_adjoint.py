@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import PERIODIC, WALL, Oracle
+from oracle import PERIODIC, WALL, Oracle, OracleQ
 from paper_2208_05429_amd import workloads as wl
 from paper_2208_05429_amd import capi
 from paper_2208_05429_amd.adjoint import force_gradient
@@ -292,6 +292,111 @@ def test_16bit_force_gradient_does_not_depend_on_the_checkpoint_interval(storage
         L, g = out[ck]
         assert L == L0, ck
         assert torch.equal(g, g0), (ck, (g - g0).abs().max().item())
+
+
+# ---------------------------------------------------------------------------
+# D3Q15 and D3Q27: the seed and one reverse step per call (the merged
+# two-step adjoint is built for D3Q19), against the adjoint of the oracle of
+# the set (pinned on the CPU by differences of its forward step)
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_sets_adjoint_seed_and_one_step_match_oracle(q, storage, tol):
+    shape = (10, 13, 12)
+    rho0, u0 = _init(shape, 31)
+    F = wl.normal_field(shape, 1e-4, 32)
+    o = OracleQ(shape, 0.8, q, faces=FACES)
+    f_t = o.run(o.init(rho0, u0), 3, F)
+    lam_next = wl.normal_field(shape, 1.0, 33, comps=q)
+    ut = wl.normal_field(shape, 1e-2, 34)
+    seed_ref, gseed_ref = o.loss_seed(f_t, ut, F)
+    lam_ref, g_ref = o.adjoint_step(f_t, lam_next, F)
+
+    rdt = real_dtype(storage)
+    print(f"[gpu] D3Q{q} adjoint {storage}", flush=True)
+    lat = Lattice(shape, 0.8, storage, "swap2", NAMES, force=torch.as_tensor(F), rho0=torch.as_tensor(rho0),
+                  u0=torch.as_tensor(u0), velocities=q)
+    lat.step(3)
+    _, u, _, _ = lat.macroscopic(want=("u",))
+    gu = (2 * (u - torch.as_tensor(ut, device=u.device))).to(rdt).contiguous()
+    lam = torch.empty((q,) + shape, dtype=rdt, device="cuda")
+    gF = torch.zeros((3,) + shape, dtype=rdt, device="cuda")
+    capi.lbm_macro_adjoint(lat.ctx, lat.f.data_ptr(), gu.data_ptr(), lam.data_ptr(), gF.data_ptr())
+    torch.cuda.synchronize()
+    e = np.abs(lam.double().cpu().numpy() - seed_ref).max() / np.abs(seed_ref).max()
+    assert e <= 10 * tol, e
+    assert np.abs(gF.double().cpu().numpy() - gseed_ref).max() <= 10 * tol * np.abs(gseed_ref).max()
+
+    lin = torch.as_tensor(lam_next, dtype=rdt, device="cuda").contiguous()
+    lout = torch.empty_like(lin)
+    g = torch.zeros((3,) + shape, dtype=rdt, device="cuda")
+    capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), lout.data_ptr(), g.data_ptr(), 1)
+    torch.cuda.synchronize()
+    e = np.abs(lout.double().cpu().numpy() - lam_ref).max() / np.abs(lam_ref).max()
+    assert e <= 10 * tol, e
+    eg = np.abs(g.double().cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
+    assert eg <= 10 * tol, eg
+    with pytest.raises(capi.LbmError) as err:  # two merged reverse steps: D3Q19 only
+        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), lout.data_ptr(), g.data_ptr(), 2)
+    assert err.value.status == capi.LBM_EUNSUPPORTED
+    lat.close()
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_sets_force_gradient_matches_oracle_adjoint(q, storage):
+    # through autograd with single reverse steps, checkpoint every 4 steps
+    shape, steps = (16, 12, 10), 12
+    rho0, u0 = _init(shape, 41)
+    o = OracleQ(shape, 0.8, q, faces=FACES)
+    f0 = o.init(rho0, u0)
+    F = wl.normal_field(shape, 1e-6, 42)
+    _, ut, _ = o.macro(o.run(f0, steps, wl.normal_field(shape, 1e-6, 43)))
+    L_ref, g_ref = o.loss_and_grad(f0, F, ut, steps)
+    lat0 = Lattice(shape, 0.8, storage, "swap2", NAMES, rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0),
+                   velocities=q)
+    f0_dev = lat0.f.clone()
+    lat0.close()
+    spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=4, merged=False)
+    L, g = force_gradient(torch.as_tensor(F, device="cuda"), f0_dev, spec, torch.as_tensor(ut, device="cuda"))
+    g = g.double().cpu().numpy()
+    assert abs(L - L_ref) <= (1e-10 if storage == "f64" else 1e-3) * L_ref
+    err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"D3Q{q} {storage}: gradient error vs the set oracle's adjoint {err:.3e}")
+    assert err <= (1e-10 if storage == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_sets_16bit_adjoint_equals_fp32_adjoint_on_the_decoded_state(q, storage):
+    shape = (9, 30, 70)
+    rho0, u0 = _init(shape, 51)
+    F = torch.as_tensor(wl.normal_field(shape, 1e-4, 52))
+    lat16 = Lattice(shape, 0.8, storage, "swap2", NAMES, force=F, rho0=torch.as_tensor(rho0),
+                    u0=torch.as_tensor(u0), velocities=q)
+    lat16.step(3)
+    lat32 = Lattice(shape, 0.8, "f32", "swap2", NAMES, force=F, f=lat16.f.to(torch.float32).contiguous(),
+                    velocities=q)
+    torch.cuda.synchronize()
+    gu = torch.as_tensor(wl.normal_field(shape, 1e-2, 53), dtype=torch.float32, device="cuda").contiguous()
+    lam_next = torch.as_tensor(wl.normal_field(shape, 1.0, 54, comps=q), dtype=torch.float32,
+                               device="cuda").contiguous()
+
+    def adjoints(lat):
+        lam = torch.empty((q,) + shape, dtype=torch.float32, device="cuda")
+        gF = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
+        capi.lbm_macro_adjoint(lat.ctx, lat.f.data_ptr(), gu.data_ptr(), lam.data_ptr(), gF.data_ptr())
+        lout = torch.empty_like(lam_next)
+        g = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
+        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lam_next.data_ptr(), lout.data_ptr(), g.data_ptr(), 1)
+        torch.cuda.synchronize()
+        return [lam, gF, lout, g]
+
+    for i, (x, y) in enumerate(zip(adjoints(lat16), adjoints(lat32))):
+        assert torch.isfinite(x).all() and x.abs().max() > 0, i
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32)), (i, (x - y).abs().max().item())
+    lat16.close()
+    lat32.close()
 
 
 def test_step_adjoint_rejects_overlapping_lambda():

@@ -35,7 +35,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
 # are built from (the kernels' code and the host's choice of shape, segments
 # and grid); stored counters of those kernels carry this digest
 MARCH_SOURCES = ("d3q19.hpp", "lattices.hpp", "lbm_internal.hpp", "march.hpp", "march_pr.hpp", "march_dispatch.hpp",
-                 "march_f32.hip", "lbm_api.cpp")
+                 "march_f32.hip", "march_plan.hpp", "march_plan.cpp")
 
 
 def source_digest(names=MARCH_SOURCES) -> str:

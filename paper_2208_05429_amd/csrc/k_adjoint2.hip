@@ -31,6 +31,8 @@
 // Bytes per cell and pass: f_t (19 s), lambda_{t+2} and lambda_t (2 x 19 x r),
 // F (3 r) and the read-modify-write of dL/dF (6 r); 132 B per lattice update
 // at FP32.
+#include <atomic>
+
 #include "adjoint_core.hpp"
 #include "march.hpp"
 
@@ -349,18 +351,24 @@ static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, c
     // Work items (tile, x segment) run in waves of `resident` workgroups, and
     // one item costs its segment length plus the 4 planes that fill its
     // pipeline.  Take the segment count that minimises waves x (length + 4).
-    static int resident_of[4] = {0, 0, 0, 0};  // per kernel variant (walls, force)
-    int& resident = resident_of[(walls ? 2 : 0) + (force ? 1 : 0)];
+    // The count is looked up once per device and kernel variant (walls,
+    // force) and kept; concurrent first calls compute the same value.
+    constexpr int kDevices = 64;
+    static std::atomic<int> resident_of[kDevices][4];  // static storage: zero until looked up
+    const int variant = (walls ? 2 : 0) + (force ? 1 : 0);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) dev = -1;
+    int resident = dev >= 0 ? resident_of[dev][variant].load(std::memory_order_relaxed) : 0;
     if (resident == 0) {
-        int dev = 0, cus = 0, per = 0;
+        int cus = 0, per = 0;
         auto k = walls ? (force ? k_adjoint2<S, TY, TZ, NT, true, true> : k_adjoint2<S, TY, TZ, NT, true, false>)
                        : (force ? k_adjoint2<S, TY, TZ, NT, false, true> : k_adjoint2<S, TY, TZ, NT, false, false>);
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        if (dev >= 0 && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, NT, 0) == hipSuccess && cus * per > 0)
             resident = cus * per;
         else
             resident = 256;
+        if (dev >= 0) resident_of[dev][variant].store(resident, std::memory_order_relaxed);
     }
     const long long tiles = (long long)a.nty * a.ntz;
     long long best = -1;

@@ -63,7 +63,7 @@ typedef struct lbm_ctx lbm_ctx;
 typedef enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,       /* bad argument: tau <= 1/2, dims < 1, null pointer, bad face codes */
-    LBM_EUNSUPPORTED = -2, /* valid but not built: e.g. the merged adjoint of D3Q15/D3Q27 */
+    LBM_EUNSUPPORTED = -2, /* valid but not built: e.g. three merged steps for D3Q15/D3Q27 */
     LBM_EDEVICE = -3,      /* a HIP call or kernel launch failed; message kept */
     LBM_ESTATE = -4        /* call on a NULL or failed context */
 } lbm_status;
@@ -98,8 +98,8 @@ typedef struct {
     int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes */
     int32_t velocities; /* velocity set: 0 or 19 = D3Q19 (the paper's); 15 = D3Q15, 27 = D3Q27 (Sec. 4.1 names
                            both as sets the two-step rule holds for): every storage (16-bit: the default
-                           tiles), LBM_TWO_ARRAY, LBM_SWAP1 and LBM_SWAP2 (large planes in rounds), the adjoint
-                           one step per call; no probes */
+                           tiles), LBM_TWO_ARRAY, LBM_SWAP1 and LBM_SWAP2 (large planes in rounds), the adjoint;
+                           no probes */
 } lbm_config;
 
 /* Bytes the caller must provide for the distribution buffer (Q*N values of
@@ -207,8 +207,8 @@ lbm_status lbm_macro_adjoint(lbm_ctx* ctx, const void* f_dev, const void* grad_u
  * merged pass of Sec. 4.1 (132 bytes per lattice update at FP32).  Every
  * storage: with FP16/BF16 the state is decoded and the adjoint computes in
  * FP32, the adjoint of the FP32 arithmetic between 16-bit stores (rounding
- * has no useful derivative).  D3Q15/D3Q27: k = 1 only (lambda buffers of
- * Q N values; k = 2 returns LBM_EUNSUPPORTED). */
+ * has no useful derivative).  Every velocity set (lambda buffers of Q N
+ * values). */
 lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambda_in_dev, void* lambda_out_dev,
                             void* grad_force_dev, int32_t k);
 

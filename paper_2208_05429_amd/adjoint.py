@@ -9,8 +9,7 @@ each checkpoint interval in reverse: recompute the states the reverse steps star
 out of place, so no state is ever copied), and run the adjoint backwards
 (lbm_step_adjoint), accumulating dL/dF.  With spec["merged"] the reverse
 steps go two at a time (the adjoint of the merged pass, f_{t+1} recomputed on
-chip), so only every other state is needed (D3Q19; the D3Q15 and D3Q27
-sets reverse one step per call).
+chip), so only every other state is needed.
 """
 from __future__ import annotations
 

@@ -218,12 +218,12 @@ static hipError_t adjoint1_set(int storage, bool force, const Geom& g, const voi
 hipError_t launch_step_adjoint(int storage, bool force, int k, const Geom& g, const void* f_t, const void* F,
                                const void* lam_in, void* lam_out, void* grad_force, hipStream_t s)
 {
-    if (g.lat != 19) {  // one reverse step per call (the merged two-step adjoint is built for D3Q19)
+    if (k == 2) return launch_step_adjoint2(storage, g, f_t, force ? F : nullptr, lam_in, lam_out, grad_force, s);
+    if (g.lat != 19) {
         if (k != 1) return hipErrorInvalidValue;
         return g.lat == 15 ? adjoint1_set<D3Q15>(storage, force, g, f_t, F, lam_in, lam_out, grad_force, s)
                            : adjoint1_set<D3Q27>(storage, force, g, f_t, F, lam_in, lam_out, grad_force, s);
     }
-    if (k == 2) return launch_step_adjoint2(storage, g, f_t, force ? F : nullptr, lam_in, lam_out, grad_force, s);
     if (k != 1) return hipErrorInvalidValue;
     switch (storage) {
     case ST_F64:

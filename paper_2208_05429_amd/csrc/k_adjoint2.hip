@@ -39,12 +39,12 @@
 namespace lbm {
 
 // nu_p = v_opp(p): the relabelling between lambda and a forward-moving field
-template <class R>
-__device__ __forceinline__ void opp_relabel(const R (&src)[Q], R (&dst)[Q])
+template <class LT, class R>
+__device__ __forceinline__ void opp_relabel(const R (&src)[LT::Q], R (&dst)[LT::Q])
 {
-    sfor<0, Q>([&](auto qc) {
+    sfor<0, LT::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        dst[q] = src[oppq(q)];
+        dst[q] = src[LT::opp(q)];
     });
 }
 
@@ -54,7 +54,7 @@ struct Adj2Shape {
     static constexpr int WZ1 = TZ + 2, NC1 = (TY + 2) * WZ1;  // tile plus one halo cell
 };
 
-template <int S, int TY, int TZ, int NT, bool WALLS, bool FORCE>
+template <int S, int TY, int TZ, int NT, bool WALLS, bool FORCE, class LT = D3Q19>
 __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
 {
     using Cd = Codec<S>;
@@ -63,12 +63,16 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
     using Sh = Adj2Shape<TY, TZ>;
     constexpr int WZ2 = Sh::WZ2, NC2 = Sh::NC2, WZ1 = Sh::WZ1, NC1 = Sh::NC1;
     static_assert(NC2 <= NT, "one frame column per thread");
-    constexpr uint32_t CXP = mask_cx(1), CXM = mask_cx(-1);
+    constexpr int QL = LT::Q;         // velocities
+    constexpr int NYZ = nyz<LT>();    // those exchanged through LDS
+    constexpr int NXP = nxp<LT>();    // those with c_x = +1, carried to the next plane
+    constexpr int XP = LT::H + 1;     // the x-only direction (+1, 0, 0); (-1, 0, 0) is 1
+    constexpr uint32_t CXP = mask_cx<LT>(1), CXM = mask_cx<LT>(-1);
 
-    __shared__ R XF[16 * NC2];  // forward recompute: post-collision f_t
-    __shared__ R XA[16 * NC2];  // nu of lambda_{t+2}
-    __shared__ R XC[16 * NC1];  // nu of lambda_{t+1}
-    __shared__ R WT[WALLS ? Q : 1];
+    __shared__ R XF[NYZ * NC2];  // forward recompute: post-collision f_t
+    __shared__ R XA[NYZ * NC2];  // nu of lambda_{t+2}
+    __shared__ R XC[NYZ * NC1];  // nu of lambda_{t+1}
+    __shared__ R WT[WALLS ? QL : 1];
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
     const bool wallx = g.wall[0] != 0;
     const R omega = R(g.omega);
     const long long N = g.N, PL = g.PL;
-    if constexpr (WALLS) wall_terms_to(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
+    if constexpr (WALLS) wall_terms_to_l<LT>(WT, tid, R(g.uw[0]), R(g.uw[1]), R(g.uw[2]));
 
     // ---- this thread's column of the frame ----
     const int c = tid;
@@ -107,10 +111,10 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
                 rad = dy > dz ? dy : dz;
                 ci1 = (ly - 1) * WZ1 + (lz - 1);
                 if constexpr (WALLS) {
-                    sfor<1, Q>([&](auto qc) {
+                    sfor<1, QL>([&](auto qc) {
                         constexpr int q = decltype(qc)::value;
-                        if constexpr (moves_yz(q)) {
-                            const int ys = y - cyq(q), zs = z - czq(q);
+                        if constexpr (moves_yz_l<LT>(q)) {
+                            const int ys = y - LT::cy(q), zs = z - LT::cz(q);
                             int f1 = -1, f2 = -1;
                             if (g.wall[1] && ys < 0) f1 = 2;
                             if (g.wall[1] && ys >= g.ny) f1 = 3;
@@ -140,19 +144,19 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
     auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
 
     // ---- registers of the three exchange levels and the histories ----
-    T Lf[Q];  // raw f_t of the next plane
-    R La[Q];  // lambda_{t+2} of the next plane
+    T Lf[QL];  // raw f_t of the next plane
+    R La[QL];  // lambda_{t+2} of the next plane
     R Fl[3] = {R(0), R(0), R(0)}, gFl[3] = {R(0), R(0), R(0)};
-    R accA[Q], accB[Q], accC[Q], nxtA[5], nxtB[5], nxtC[5];
+    R accA[QL], accB[QL], accC[QL], nxtA[NXP], nxtB[NXP], nxtC[NXP];
     R oA[3], oB[3], oC[3];
     R Fh1[3], Fh2[3], mh1[4], mh2[4], gFp[3];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < QL; ++q) {
         Lf[q] = T(0);
         La[q] = accA[q] = accB[q] = accC[q] = R(0);
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) nxtA[j] = nxtB[j] = nxtC[j] = R(0);
+    for (int j = 0; j < NXP; ++j) nxtA[j] = nxtB[j] = nxtC[j] = R(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) oA[j] = oB[j] = oC[j] = Fh1[j] = Fh2[j] = gFp[j] = R(0);
 #pragma unroll
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
         const int px = wrapi(xp, g.nx);
         const T* bf = ft + (long long)px * PL;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             Lf[q] = Buf<T>::ld(make_rsrc(bf, live ? planeT : 0u), loffT);
             bf += N;
         }
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
         const int px = wrapi(xp, g.nx);
         const R* bl = lin + (long long)px * PL;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < QL; ++q) {
             La[q] = Buf<R>::ld(make_rsrc(bl, live ? planeR : 0u), loffR);
             bl += N;
         }
@@ -221,36 +225,36 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
             gFo[k] = gFl[k];
         }
         const bool s1 = present(P) && loads;
-        R v[Q];
+        R v[QL];
         if (s1) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) v[q] = Cd::dec(Lf[q]);
-            R nu[Q];
-            opp_relabel(La, nu);
-            sfor<0, Q>([&](auto qc) {
+            for (int q = 0; q < QL; ++q) v[q] = Cd::dec(Lf[q]);
+            R nu[QL];
+            opp_relabel<LT>(La, nu);
+            sfor<0, QL>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                if constexpr (moves_yz(q)) XA[yz_index(q) * NC2 + c] = nu[q];
+                if constexpr (moves_yz_l<LT>(q)) XA[yz_index_l<LT>(q) * NC2 + c] = nu[q];
             });
             oB[0] = nu[0];
             oB[1] = nu[1];
-            oB[2] = nu[10];
+            oB[2] = nu[XP];
         }
         issue_l(P + 1, i + 1 < total);
         if (s1) {
-            const Moments<R> m = moments<R, FORCE>(v, Fc[0], Fc[1], Fc[2]);
+            const Moments<R> m = moments_l<R, FORCE, LT>(v, Fc[0], Fc[1], Fc[2]);
             mc[0] = m.rho;
             mc[1] = m.ux;
             mc[2] = m.uy;
             mc[3] = m.uz;
-            collide<R, FORCE>(v, omega, Fc[0], Fc[1], Fc[2]);
-            sfor<0, Q>([&](auto qc) {
+            LT::template collide<R, FORCE>(v, omega, Fc[0], Fc[1], Fc[2]);
+            sfor<0, QL>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                if constexpr (moves_yz(q)) XF[yz_index(q) * NC2 + c] = v[q];
+                if constexpr (moves_yz_l<LT>(q)) XF[yz_index_l<LT>(q) * NC2 + c] = v[q];
             });
-            if constexpr (WALLS) moving_wall_out(v[1], v[10], XF, NC2, c, myz | xm(P), WT);
+            if constexpr (WALLS) moving_wall_out_l<LT>(v[1], v[XP], XF, NC2, c, myz | xm(P), WT);
             oA[0] = v[0];
             oA[1] = v[1];
-            oA[2] = v[10];
+            oA[2] = v[XP];
         }
         issue_f(P + 1, i + 1 < total);
         __syncthreads();
@@ -259,51 +263,51 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
         R gFa[3] = {R(0), R(0), R(0)};
         if (rad <= 1 && gofs >= 0) {
             const uint32_t bd = byz | xb(P - 1), bn = byz | xb(P);
-            complete<R, WALLS>(accA, XF, NC2, c, WZ2, oA[1], bd);
-            complete<R, WALLS>(accB, XA, NC2, c, WZ2, oB[1], bd);
+            complete<R, WALLS, LT>(accA, XF, NC2, c, WZ2, oA[1], bd);
+            complete<R, WALLS, LT>(accB, XA, NC2, c, WZ2, oB[1], bd);
             if (present(P - 1)) {
-                R mu[Q], lam[Q], nu[Q];
-                opp_relabel(accB, mu);
-                collide_adjoint<R, FORCE>(accA, mu, omega, Fh1[0], Fh1[1], Fh1[2], lam, gFa[0], gFa[1], gFa[2]);
-                opp_relabel(lam, nu);
-                sfor<0, Q>([&](auto qc) {
+                R mu[QL], lam[QL], nu[QL];
+                opp_relabel<LT>(accB, mu);
+                collide_adjoint<R, FORCE, LT>(accA, mu, omega, Fh1[0], Fh1[1], Fh1[2], lam, gFa[0], gFa[1], gFa[2]);
+                opp_relabel<LT>(lam, nu);
+                sfor<0, QL>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
-                    if constexpr (moves_yz(q)) XC[yz_index(q) * NC1 + ci1] = nu[q];
+                    if constexpr (moves_yz_l<LT>(q)) XC[yz_index_l<LT>(q) * NC1 + ci1] = nu[q];
                 });
                 oC[0] = nu[0];
                 oC[1] = nu[1];
-                oC[2] = nu[10];
+                oC[2] = nu[XP];
             }
-            deposit<R, WALLS>(accA, nxtA, XF, NC2, c, WZ2, oA[0], oA[1], oA[2], bn);
-            deposit<R, WALLS>(accB, nxtB, XA, NC2, c, WZ2, oB[0], oB[1], oB[2], bn);
+            deposit<R, WALLS, LT>(accA, nxtA, XF, NC2, c, WZ2, oA[0], oA[1], oA[2], bn);
+            deposit<R, WALLS, LT>(accB, nxtB, XA, NC2, c, WZ2, oB[0], oB[1], oB[2], bn);
         }
         __syncthreads();
 
         // ---- S3: plane P-2 on the tile: lambda_t and dL/dF ----
         const int po = P - 2;
         const bool out = po >= s && po < e && present(po);
-        R lam0[Q], go[3];
+        R lam0[QL], go[3];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) lam0[q] = R(0);
+        for (int q = 0; q < QL; ++q) lam0[q] = R(0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) go[k] = R(0);
         if (rad == 0 && gofs >= 0) {
-            complete<R, WALLS>(accC, XC, NC1, ci1, WZ1, oC[1], byz | xb(po));
+            complete<R, WALLS, LT>(accC, XC, NC1, ci1, WZ1, oC[1], byz | xb(po));
             if (out) {
-                R mu[Q], gx, gy, gz;
-                opp_relabel(accC, mu);
-                collide_adjoint_m<R, FORCE>(mh2[0], mh2[1], mh2[2], mh2[3], mu, omega, Fh2[0], Fh2[1], Fh2[2], lam0,
-                                            gx, gy, gz);
+                R mu[QL], gx, gy, gz;
+                opp_relabel<LT>(accC, mu);
+                collide_adjoint_m<R, FORCE, LT>(mh2[0], mh2[1], mh2[2], mh2[3], mu, omega, Fh2[0], Fh2[1], Fh2[2],
+                                                lam0, gx, gy, gz);
                 go[0] = gFo[0] + (gFp[0] + gx);
                 go[1] = gFo[1] + (gFp[1] + gy);
                 go[2] = gFo[2] + (gFp[2] + gz);
             }
-            deposit<R, WALLS>(accC, nxtC, XC, NC1, ci1, WZ1, oC[0], oC[1], oC[2], byz | xb(P - 1));
+            deposit<R, WALLS, LT>(accC, nxtC, XC, NC1, ci1, WZ1, oC[0], oC[1], oC[2], byz | xb(P - 1));
         }
         {
             const R* bq = lout + (long long)wrapi(po, g.nx) * PL;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
+            for (int q = 0; q < QL; ++q) {
                 Buf<R>::st(lam0[q], make_rsrc(bq, out ? planeR : 0u), ooffR);
                 bq += N;
             }
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_adjoint2(Adj2Args a)
     }
 }
 
-template <int S, int TY, int TZ, int NT>
+template <int S, int TY, int TZ, int NT, class LT = D3Q19>
 static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, const void* lin, void* lout, void* gF,
                                  hipStream_t st)
 {
@@ -361,8 +365,8 @@ static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, c
     int resident = dev >= 0 ? resident_of[dev][variant].load(std::memory_order_relaxed) : 0;
     if (resident == 0) {
         int cus = 0, per = 0;
-        auto k = walls ? (force ? k_adjoint2<S, TY, TZ, NT, true, true> : k_adjoint2<S, TY, TZ, NT, true, false>)
-                       : (force ? k_adjoint2<S, TY, TZ, NT, false, true> : k_adjoint2<S, TY, TZ, NT, false, false>);
+        auto k = walls ? (force ? k_adjoint2<S, TY, TZ, NT, true, true, LT> : k_adjoint2<S, TY, TZ, NT, true, false, LT>)
+                       : (force ? k_adjoint2<S, TY, TZ, NT, false, true, LT> : k_adjoint2<S, TY, TZ, NT, false, false, LT>);
         if (dev >= 0 && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, NT, 0) == hipSuccess && cus * per > 0)
             resident = cus * per;
@@ -388,14 +392,14 @@ static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, c
     const dim3 grid(unsigned((a.items + 7) / 8 * 8));
     if (walls) {
         if (force)
-            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, true>), grid, dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, true, LT>), grid, dim3(NT), 0, st, a);
         else
-            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, false>), grid, dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, true, false, LT>), grid, dim3(NT), 0, st, a);
     } else {
         if (force)
-            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, false, true>), grid, dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, false, true, LT>), grid, dim3(NT), 0, st, a);
         else
-            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, false, false>), grid, dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_adjoint2<S, TY, TZ, NT, false, false, LT>), grid, dim3(NT), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -406,26 +410,35 @@ static hipError_t adjoint2_shape(const Geom& g, const void* ft, const void* F, c
 // exactly; 16 % faster than 16 x 16 at 256^3) unless its ragged edge tiles
 // make 16 x 16 cheaper (a 64 x 64 plane: 18 tiles against 16).  The choice
 // depends on the lattice only, so every storage takes the same tiles.
-template <int S>
+template <int S, class LT>
 static hipError_t adjoint2_r32(const Geom& g, const void* f_t, const void* F, const void* lam_in, void* lam_out,
                                void* grad_force, hipStream_t s)
 {
     const long long t1228 = (long long)((g.ny + 11) / 12) * ((g.nz + 27) / 28);
     const long long t1616 = (long long)((g.ny + 15) / 16) * ((g.nz + 15) / 16);
-    if (t1616 < t1228) return adjoint2_shape<S, 16, 16, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    return adjoint2_shape<S, 12, 28, 512>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    if (t1616 < t1228) return adjoint2_shape<S, 16, 16, 512, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    return adjoint2_shape<S, 12, 28, 512, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+}
+
+template <class LT>
+static hipError_t adjoint2_set(int storage, const Geom& g, const void* f_t, const void* F, const void* lam_in,
+                               void* lam_out, void* grad_force, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return adjoint2_shape<ST_F64, 8, 8, 256, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F32: return adjoint2_r32<ST_F32, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_F16: return adjoint2_r32<ST_F16, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    case ST_BF16: return adjoint2_r32<ST_BF16, LT>(g, f_t, F, lam_in, lam_out, grad_force, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step_adjoint2(int storage, const Geom& g, const void* f_t, const void* F, const void* lam_in,
                                 void* lam_out, void* grad_force, hipStream_t s)
 {
-    switch (storage) {
-    case ST_F64: return adjoint2_shape<ST_F64, 8, 8, 256>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    case ST_F32: return adjoint2_r32<ST_F32>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    case ST_F16: return adjoint2_r32<ST_F16>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    case ST_BF16: return adjoint2_r32<ST_BF16>(g, f_t, F, lam_in, lam_out, grad_force, s);
-    }
-    return hipErrorInvalidValue;
+    if (g.lat == 15) return adjoint2_set<D3Q15>(storage, g, f_t, F, lam_in, lam_out, grad_force, s);
+    if (g.lat == 27) return adjoint2_set<D3Q27>(storage, g, f_t, F, lam_in, lam_out, grad_force, s);
+    return adjoint2_set<D3Q19>(storage, g, f_t, F, lam_in, lam_out, grad_force, s);
 }
 
 }  // namespace lbm

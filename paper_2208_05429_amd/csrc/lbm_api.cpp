@@ -484,8 +484,6 @@ lbm_status lbm_step_adjoint(lbm_ctx* ctx, const void* f_t_dev, const void* lambd
     if (check_ctx(ctx) != LBM_OK) return LBM_ESTATE;
     ctx->err.clear();
     if (k != 1 && k != 2) return fail(&ctx->err, LBM_EINVAL, "k must be 1 or 2");
-    if (ctx->g.lat != 19 && k != 1)
-        return fail(&ctx->err, LBM_EUNSUPPORTED, "the merged (k = 2) adjoint is built for D3Q19 only");
     if (!f_t_dev || !lambda_in_dev || !lambda_out_dev)
         return fail(&ctx->err, LBM_EINVAL, "f_t, lambda_in and lambda_out are required");
     if (ctx->force && !grad_force_dev) return fail(&ctx->err, LBM_EINVAL, "grad_force is required with a force");

@@ -295,9 +295,9 @@ def test_16bit_force_gradient_does_not_depend_on_the_checkpoint_interval(storage
 
 
 # ---------------------------------------------------------------------------
-# D3Q15 and D3Q27: the seed and one reverse step per call (the merged
-# two-step adjoint is built for D3Q19), against the adjoint of the oracle of
-# the set (pinned on the CPU by differences of its forward step)
+# D3Q15 and D3Q27: the seed, one reverse step and two merged reverse steps,
+# against the adjoint of the oracle of the set (pinned on the CPU by
+# differences of its forward step)
 
 @pytest.mark.parametrize("q", [15, 27])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
@@ -336,9 +336,6 @@ def test_sets_adjoint_seed_and_one_step_match_oracle(q, storage, tol):
     assert e <= 10 * tol, e
     eg = np.abs(g.double().cpu().numpy() - g_ref).max() / np.abs(g_ref).max()
     assert eg <= 10 * tol, eg
-    with pytest.raises(capi.LbmError) as err:  # two merged reverse steps: D3Q19 only
-        capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), lout.data_ptr(), g.data_ptr(), 2)
-    assert err.value.status == capi.LBM_EUNSUPPORTED
     lat.close()
 
 
@@ -364,6 +361,65 @@ def test_sets_force_gradient_matches_oracle_adjoint(q, storage):
     err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
     print(f"D3Q{q} {storage}: gradient error vs the set oracle's adjoint {err:.3e}")
     assert err <= (1e-10 if storage == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+@pytest.mark.parametrize("case", [0, 2, 4])
+def test_sets_merged_adjoint_matches_the_oracle(q, storage, tol, case):
+    # k = 2: f_{t+1} recomputed on chip, against two reverse steps of the set
+    # oracle (case 0: 16 x 16 adjoint tiles; 2, 4: 12 x 28, walls, a lid, force)
+    shape, faces, wall_u, with_force = MERGED_CASES[case]
+    names = [{PERIODIC: "periodic", WALL: "wall", 2: "moving"}[f] for f in faces]
+    print(f"[gpu] D3Q{q} merged adjoint {storage} {shape} {names} force={with_force}", flush=True)
+    rho0, u0 = _init(shape, 61 + case)
+    F = wl.normal_field(shape, 1e-4, 62 + case) if with_force else None
+    o = OracleQ(shape, 0.7, q, faces=faces, wall_u=wall_u)
+    f_t = o.run(o.init(rho0, u0), 2, F)
+    f_t1 = o.run(f_t, 1, F)
+    lam2 = wl.normal_field(shape, 1.0, 63 + case, comps=q)
+    lam1, g1 = o.adjoint_step(f_t1, lam2, F)
+    lam0, g0 = o.adjoint_step(f_t, lam1, F, g1)
+
+    rdt = real_dtype(storage)
+    lat = Lattice(shape, 0.7, storage, "swap2", names, wall_u, force=None if F is None else torch.as_tensor(F),
+                  rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0), velocities=q)
+    lat.step(2)
+    lin = torch.as_tensor(lam2, dtype=rdt, device="cuda").contiguous()
+    lout = torch.empty_like(lin)
+    gF = torch.zeros((3,) + shape, dtype=rdt, device="cuda")
+    capi.lbm_step_adjoint(lat.ctx, lat.f.data_ptr(), lin.data_ptr(), lout.data_ptr(),
+                          gF.data_ptr() if F is not None else None, 2)
+    torch.cuda.synchronize()
+    e = np.abs(lout.double().cpu().numpy() - lam0).max() / np.abs(lam0).max()
+    assert e <= 10 * tol, e
+    if F is not None:
+        eg = np.abs(gF.double().cpu().numpy() - g0).max() / np.abs(g0).max()
+        assert eg <= 10 * tol, eg
+    lat.close()
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_sets_force_gradient_merged_matches_oracle_adjoint(q, storage):
+    shape, steps = (16, 12, 10), 12
+    rho0, u0 = _init(shape, 71)
+    o = OracleQ(shape, 0.8, q, faces=FACES)
+    f0 = o.init(rho0, u0)
+    F = wl.normal_field(shape, 1e-6, 72)
+    _, ut, _ = o.macro(o.run(f0, steps, wl.normal_field(shape, 1e-6, 73)))
+    L_ref, g_ref = o.loss_and_grad(f0, F, ut, steps)
+    lat0 = Lattice(shape, 0.8, storage, "swap2", NAMES, rho0=torch.as_tensor(rho0), u0=torch.as_tensor(u0),
+                   velocities=q)
+    f0_dev = lat0.f.clone()
+    lat0.close()
+    for ck in (4, 5):  # even and odd checkpoint segments (odd ones end with one single reverse step)
+        spec = dict(shape=shape, tau=0.8, storage=storage, faces=NAMES, steps=steps, checkpoint=ck, merged=True)
+        L, g = force_gradient(torch.as_tensor(F, device="cuda"), f0_dev, spec, torch.as_tensor(ut, device="cuda"))
+        g = g.double().cpu().numpy()
+        err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+        print(f"D3Q{q} {storage} checkpoint {ck}: merged-adjoint gradient error {err:.3e}")
+        assert err <= (1e-10 if storage == "f64" else 1e-3)
 
 
 @pytest.mark.parametrize("q", [15, 27])

@@ -1,5 +1,7 @@
 """GPU discrete adjoint (through the C ABI) against the FP64 oracle's adjoint,
-and the whole-run force gradient against central finite differences."""
+and the whole-run force gradient against central finite differences; 16-bit
+storage against the FP32 adjoint on the decoded state; D3Q15 and D3Q27
+against the adjoint of the oracle of the set."""
 import numpy as np
 import pytest
 import torch

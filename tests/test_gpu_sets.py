@@ -4,7 +4,9 @@ of the same set (oracle/lbm_oracle_q.c, pinned on the CPU): every scheme,
 FP64 within 1e-12 and FP32 within 2e-6 of the oracle per field, and the
 in-place single-copy schemes equal to the two-array kernel to the bit (the
 same per-cell arithmetic).  Ragged tiles, walls, a moving lid, a body force,
-odd step counts; FP32 over 100 steps on the 32^3 Taylor-Green vortex."""
+odd step counts; FP32 over 100 steps on the 32^3 Taylor-Green vortex; planes
+in rounds; FP16/BF16 storage pinned by the half-ulp bound of one store.  (The
+sets' adjoint is tested in test_gpu_adjoint.py.)"""
 import numpy as np
 import pytest
 import torch

@@ -39,6 +39,7 @@ struct MarchPlan {
     // bands of nty_band tile rows (both kernel layouts)
     int nbands = 1, nty_band = 0;
     size_t shell_bytes = 0;      // the M boundary rows of every band, all x: nbands * 2 * M rows
+    int lockstep = 0;            // 1: a plane is stored once the neighbours finished the previous iteration
 };
 
 struct MarchArgs {

@@ -122,7 +122,11 @@ struct ShapeList {
 struct ShapeEntry {
     int M, TY, TZ, NT, pr, pf;
 };
-constexpr ShapeEntry kShapesF64[] = {{2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}};
+// FP64: 10 x 32 tiles first (rows of 32 doubles are whole cache lines, and a
+// 1024-wide plane takes 32 tiles per row: eight rows fill 256 workgroups),
+// 12 x 28 as variant 1.
+constexpr ShapeEntry kShapesF64[] = {{2, 10, 32, 512, 0, 1}, {1, 12, 34, 512, 0, 1},
+                                     {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}};
 constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}, {2, 16, 64, 512, 0, 1},
                                      {1, 16, 64, 512, 0, 1}, {2, 32, 32, 512, 1, 1}, {1, 32, 32, 512, 1, 1},
                                      {2, 32, 32, 512, 0, 1}, {1, 32, 32, 512, 0, 1}, {2, 16, 64, 512, 1, 2},

@@ -45,8 +45,9 @@ def _status(cfg):
     (dict(shape=(64, 1025, 1024)), capi.LBM_EUNSUPPORTED),
     # the same with odd nz (plain layout only)
     (dict(shape=(64, 1025, 1023)), capi.LBM_EUNSUPPORTED),
-    # FP64 (12-row tiles) across a periodic y seam: a last tile row thinner than the halo
-    (dict(shape=(64, 1009, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
+    # FP64 across a periodic y seam: a last tile row thinner than the halo for both
+    # tile heights built (121 = 12 x 10 + 1 = 10 x 12 + 1)
+    (dict(shape=(64, 121, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
 ])
 def test_invalid_configs_are_rejected(kw, code):
     assert _status(_cfg(**kw))[0] == code
@@ -88,14 +89,20 @@ def test_rounds_plan_for_large_planes():
     # and one thinner than the halo another tile height (1009 = 31 x 32 + 17)
     assert _status(_cfg(shape=(nx, 1000, 1024)))[0] == capi.LBM_OK
     assert _status(_cfg(shape=(nx, 1009, 1024)))[0] == capi.LBM_OK
-    # FP64 (plain layout, 12 x 28 tiles): 86 x 37 tiles, bands of 6 tile rows
-    # (256 // 37), 15 rounds, each band's 2 M boundary rows saved
-    st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024), storage=capi.LBM_F64))
-    assert st == capi.LBM_OK
-    shells = 15 * 2 * 2 * 1024 * nx * 19 * 8
-    assert shells <= wb < shells + 19 * 8 * 1024 * 1024 * 4 + (1 << 24)
+    # FP64 (plain layout, 10 x 32 tiles): 103 x 32 tiles, bands of 8 tile rows
+    # (256 // 32), 13 rounds, each band's 2 M boundary rows saved; variant 1
+    # (12 x 28 tiles): 86 x 37 tiles, bands of 6 tile rows, 15 rounds
+    for variant, rounds in ((0, 13), (1, 15)):
+        st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024), storage=capi.LBM_F64, variant=variant))
+        assert st == capi.LBM_OK
+        shells = rounds * 2 * 2 * 1024 * nx * 19 * 8
+        assert shells <= wb < shells + 19 * 8 * 1024 * 1024 * 4 + (1 << 24), (variant, wb)
     # a ragged last tile row across the periodic seam at least as thick as the halo
     assert _status(_cfg(shape=(nx, 1000, 1024), storage=capi.LBM_F64))[0] == capi.LBM_OK
+    # 1009 rows: 10-row tiles leave a last row of 9; 12-row ones (variant 1) a row of
+    # 1, so that variant falls back to the 10-row tiles there
+    for variant in (0, 1):
+        assert _status(_cfg(shape=(nx, 1009, 1024), storage=capi.LBM_F64, variant=variant))[0] == capi.LBM_OK
     # odd nz: the plain layout (16 x 64 tiles) runs the same four rounds, in every storage
     for storage, s in ((capi.LBM_F32, 4), (capi.LBM_BF16_OFS, 2), (capi.LBM_F16_OFS, 2)):
         st, fb, wb = _status(_cfg(shape=(nx, 1024, 1023), storage=storage))

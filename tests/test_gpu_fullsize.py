@@ -186,31 +186,35 @@ def test_rounds_match_two_array_bitwise(case):
     ref.close()
 
 
-# FP64 runs its plain layout (12 x 28 tiles for two steps, 14 x 30 for one) in
-# rounds; these planes need 612, 666 and 520 of those tiles.  The last case has
-# bands of a single row of tiles, so one workgroup reads saved rows both below
-# its band and across the periodic seam above it.
+# FP64 runs its plain layout in rounds: 10 x 32 tiles for two steps and
+# 12 x 34 for one (variant 0), or 12 x 28 and 14 x 30 (variant 1); these planes
+# need 640, 693, 456 and 456 tiles of the first kind, 612, 666, 520 and 520 of
+# the second.  With 12 x 28 tiles the third case has bands of a single row of
+# tiles, so one workgroup reads saved rows both below its band and across the
+# periodic seam above it.
 FP64_BANDED_CASES = [
     ((6, 200, 1000), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
     ((5, 210, 1030), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),
     ((4, 40, 3640), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
-    # a last tile row 3 cells high: across the periodic seam its rows above
-    # share waves with its own rows (the per-lane source choice)
+    # a last tile row 3 cells high (12 x 28 tiles; 9 with 10 x 32): across the
+    # periodic seam its rows above share waves with its own rows (the per-lane
+    # source choice)
     ((4, 39, 3640), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
 ]
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("case", range(len(FP64_BANDED_CASES)))
-def test_rounds_fp64_match_two_array_bitwise(case):
+def test_rounds_fp64_match_two_array_bitwise(case, variant):
     shape, faces, wall_u = FP64_BANDED_CASES[case]
     names = [_NAMES[f] for f in faces]
     rho0, u0 = wl.taylor_green_3d(shape, 0.03)
     u0 = u0 + wl.uniform_noise(shape, 5e-3, 440 + case)
     r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 441 + case)), torch.as_tensor(u0)
-    print(f"[gpu] rounds f64 {shape} {names}", flush=True)
+    print(f"[gpu] rounds f64 {shape} {names} variant {variant}", flush=True)
     ref = Lattice(shape, 0.6, "f64", "two_array", names, wall_u, rho0=r0, u0=v0)
     for scheme in ("swap2", "swap1"):
-        lat = Lattice(shape, 0.6, "f64", scheme, names, wall_u, rho0=r0, u0=v0)
+        lat = Lattice(shape, 0.6, "f64", scheme, names, wall_u, rho0=r0, u0=v0, variant=variant)
         lat.f.copy_(ref.f)
         ref_f0 = ref.f.clone()
         ref.step(3)

@@ -352,8 +352,8 @@ def test_tgv1024_fp32_merged_rounds_sampled_cells():
 
 def test_tgv1024_fp64_merged_rounds_sampled_cells():
     # 1024^3 in FP64: 163 GB of distributions, which fit the 288 GB of HBM only
-    # as a single copy (two arrays would need 326 GB); 15 rounds of bands of six
-    # 12-row tile rows per merged pass, a ragged last tile row across the seam
+    # as a single copy (two arrays would need 326 GB); 13 rounds of bands of
+    # eight 10-row tile rows per merged pass, a ragged last tile row across the seam
     cfg = wl.TGV_1024
     shape, tau, n = cfg["shape"], cfg["tau"], 4
     ph = wl.random_phases(cfg["phase_seed"])

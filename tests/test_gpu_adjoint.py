@@ -120,9 +120,9 @@ def test_force_gradient_matches_central_differences_fp64():
 
 
 # Two merged reverse steps (one pass, f_{t+1} recomputed on chip) against two
-# single reverse steps of the oracle.  Shapes span several tiles (FP32: 12x28,
-# or 16x16 where that takes fewer tiles, as for the last case; FP64: 8x8) with
-# ragged last tiles and several x segments.
+# single reverse steps of the oracle.  Shapes span several tiles (FP32: the
+# fewest tiles of 12x28, 10x32 and 16x16: 12x28 for the first four cases,
+# 10x32 for the last; FP64: 8x8) with ragged last tiles and several x segments.
 MERGED_CASES = [
     ((40, 21, 19), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
     ((24, 18, 37), (PERIODIC,) * 6, (0.0, 0.0, 0.0), True),
@@ -234,14 +234,15 @@ def test_force_gradient_does_not_depend_on_the_forward_scheme(storage):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("shape", [(10, 13, 12), (9, 30, 70)])
+@pytest.mark.parametrize("shape", [(10, 13, 12), (9, 30, 70), (8, 30, 61)])
 def test_16bit_adjoint_equals_fp32_adjoint_on_the_decoded_state(storage, shape):
     # A 16-bit offset decodes exactly into FP32 and the adjoint computes in
     # FP32 for both storages, so on the same decoded state the seed, one
     # reverse step and two merged reverse steps (f_{t+1} recomputed on chip)
     # equal the FP32 ones bit for bit; the FP32 adjoint is held to the
     # oracle's above.  (10, 13, 12) takes 16 x 16 merged-adjoint tiles,
-    # (9, 30, 70) 12 x 28 ones (several, with ragged edges).
+    # (9, 30, 70) 12 x 28 ones and (8, 30, 61) 10 x 32 ones (several, with
+    # ragged edges).
     rho0, u0 = _init(shape, 21)
     F = torch.as_tensor(wl.normal_field(shape, 1e-4, 22))
     print(f"[gpu] 16-bit adjoint {storage} {shape}", flush=True)
@@ -471,8 +472,8 @@ def test_step_adjoint_rejects_overlapping_lambda():
 
 def test_merged_adjoint_at_256_cubed_matches_two_single_steps():
     # the bench's bandwidth-bound adjoint workload: 256^3 channel with a body
-    # force, FP32, in the launch configuration it is timed in (12 x 28 tiles,
-    # eight x segments, XCD-ordered work items); the merged kernel against two
+    # force, FP32, in the launch configuration it is timed in (10 x 32 tiles,
+    # six x segments, XCD-ordered work items); the merged kernel against two
     # launches of the single-step adjoint, an independent gather formulation
     # (measured: bit-identical; the bound allows for a different rounding order)
     shape = (256, 256, 256)

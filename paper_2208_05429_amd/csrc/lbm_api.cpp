@@ -149,6 +149,12 @@ lbm_status setup(lbm_ctx* ctx, const lbm_config* cfg, void* f_dev, void* work_de
     }
     st = layout(*cfg, cap, ctx->plan, off, &total, why);
     if (st != LBM_OK) return st;
+    if (total > sized && cap < kMaxResident) {
+        // a smaller cap can leave a short last band whose own x segments need
+        // more side planes than the size reported: run it in the others'
+        st = layout(*cfg, cap, ctx->plan, off, &total, why, false);
+        if (st != LBM_OK) return st;
+    }
     if (total > sized)
         return fail(why, LBM_EUNSUPPORTED,
                     "this device holds fewer co-resident marching workgroups than the work-buffer size assumed");
@@ -232,6 +238,17 @@ lbm_status march_pass(lbm_ctx* ctx, int M, const void* src, void* dst)
         lbm_status st = device_err(ctx, launch_prepass(ctx->cfg.storage, ctx->g, p, src, side, flags, ctx->stream),
                                    "prepass launch");
         if (st != LBM_OK) return st;
+        if (p.nseg_last > 0) {
+            // the side planes of the last band's own segments (and its counters)
+            MarchPlan pl = p;
+            pl.nseg = p.nseg_last;
+            pl.seg_len = p.seg_len_last;
+            st = device_err(ctx,
+                            launch_prepass(ctx->cfg.storage, ctx->g, pl, src,
+                                           static_cast<unsigned char*>(side) + p.side_off_last, flags, ctx->stream),
+                            "prepass launch");
+            if (st != LBM_OK) return st;
+        }
         if (p.nbands > 1) {
             st = device_err(ctx, launch_shells(ctx->cfg.storage, ctx->g, p, p.TY, src, shell, ctx->stream),
                             "band boundary copy launch");

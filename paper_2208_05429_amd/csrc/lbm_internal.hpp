@@ -38,6 +38,11 @@ struct MarchPlan {
     // y-z planes with more tiles than can be co-resident run as rounds over
     // bands of nty_band tile rows (both kernel layouts)
     int nbands = 1, nty_band = 0;
+    // a last band with fewer tile rows marches in x segments of its own (more
+    // of them, to fill the device); 0: the same segments as the other bands.
+    // Its side planes follow the others' in the side buffer, at side_off_last.
+    int nseg_last = 0, seg_len_last = 0;
+    size_t side_off_last = 0;
     size_t shell_bytes = 0;      // the M boundary rows of every band, all x: nbands * 2 * M rows
     int lockstep = 0;            // 1: a plane is stored once the neighbours finished the previous iteration
 };

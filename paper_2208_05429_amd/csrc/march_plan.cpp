@@ -114,7 +114,7 @@ bool plain_shape_for_seam(int storage, int M, int ny, MarchPlan* r, int lat)
 }
 
 // Tiles, segments and the hazard neighbourhood of one marching pass.
-lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::string* why)
+lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::string* why, bool last_segments)
 {
     MarchPlan r;
     r.M = M;
@@ -179,23 +179,45 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     // step than segments of 4M planes; larger lattices run out of workgroups
     // first).  Neighbouring segments guard each other only, which needs
     // seg_len >= M.
-    int nseg = cap / tiles_run;
-    const int by_len = c.nx / (2 * M);
-    if (nseg > by_len) nseg = by_len;
-    if (nseg < 1) nseg = 1;
-    int seg_len = (c.nx + nseg - 1) / nseg;
-    nseg = (c.nx + seg_len - 1) / seg_len;
-    while (nseg > 1 && c.nx - (nseg - 1) * seg_len < 2 * M) {
-        --nseg;
-        seg_len = (c.nx + nseg - 1) / nseg;
+    auto split = [&](int items, int* nseg_out, int* len_out) {
+        int nseg = cap / items;
+        const int by_len = c.nx / (2 * M);
+        if (nseg > by_len) nseg = by_len;
+        if (nseg < 1) nseg = 1;
+        int seg_len = (c.nx + nseg - 1) / nseg;
         nseg = (c.nx + seg_len - 1) / seg_len;
-    }
-    r.nseg = nseg;
-    r.seg_len = seg_len;
+        while (nseg > 1 && c.nx - (nseg - 1) * seg_len < 2 * M) {
+            --nseg;
+            seg_len = (c.nx + nseg - 1) / nseg;
+            nseg = (c.nx + seg_len - 1) / seg_len;
+        }
+        *nseg_out = nseg;
+        *len_out = seg_len;
+    };
+    split(tiles_run, &r.nseg, &r.seg_len);
+    const int nseg = r.nseg;
     r.blocks = tiles_run * nseg;
     r.xcd_remap = (r.blocks % 8 == 0) ? 1 : 0;
     r.cap = cap;
-    r.side_bytes = size_t(nseg) * size_t(M) * size_t(lat) * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
+    const size_t side_one = size_t(M) * size_t(lat) * size_t(c.ny) * size_t(c.nz) * elem_size(c.storage);
+    r.side_bytes = size_t(nseg) * side_one;
+    int nseg_max = nseg;
+    if (r.nbands > 1 && last_segments) {
+        // A round is bound by the latency of its plane iterations, not by its
+        // bytes, so a short last band (FP64 512^3: 4 of 16 tile rows) takes
+        // nearly the time of a full one; cut into more x segments it fills
+        // the device and takes a fraction of it.
+        const int last_rows = r.nty - (r.nbands - 1) * r.nty_band;
+        int ns = 0, len = 0;
+        split(last_rows * r.ntz, &ns, &len);
+        if (ns > nseg) {
+            r.nseg_last = ns;
+            r.seg_len_last = len;
+            r.side_off_last = align_up(r.side_bytes);
+            r.side_bytes = r.side_off_last + size_t(ns) * side_one;
+            nseg_max = ns;
+        }
+    }
     r.shell_bytes = r.nbands > 1 ? size_t(r.nbands) * 2u * size_t(M) * size_t(c.nz) * size_t(c.nx) * size_t(lat) *
                                        elem_size(c.storage)
                                  : 0;
@@ -208,13 +230,14 @@ lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::str
     // wait of the hazard check; the slowest workgroup still never waits.
     r.lockstep = (r.nbands > 1 && lat == 19) ? 1 : 0;
     r.flag_stride = kFlagStride;
-    r.flag_bytes = size_t(tiles * nseg + 1) * size_t(kFlagStride) * sizeof(int);
+    r.flag_bytes = size_t(tiles * nseg_max + 1) * size_t(kFlagStride) * sizeof(int);
     *p = r;
     return LBM_OK;
 }
 
 // work buffer layout; plans use the device's co-residency cap
-lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6], size_t* total, std::string* why)
+lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6], size_t* total, std::string* why,
+                  bool last_segments)
 {
     const long long N = (long long)c.nx * c.ny * c.nz;
     size_t o = 0;
@@ -232,7 +255,7 @@ lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6
         for (int M = 1; M <= 3; ++M) {
             if (M == 2 && c.scheme != LBM_SWAP2 && c.scheme != LBM_SWAP3) continue;
             if (M == 3 && c.scheme != LBM_SWAP3) continue;
-            lbm_status st = make_plan(c, M, cap, &plans[M], why);
+            lbm_status st = make_plan(c, M, cap, &plans[M], why, last_segments);
             if (st != LBM_OK) return st;
             if (plans[M].flag_bytes > flags) flags = plans[M].flag_bytes;
             if (plans[M].side_bytes > side) side = plans[M].side_bytes;
@@ -295,11 +318,17 @@ hipError_t launch_march_pass(const lbm_config& cfg, const Geom& g, const MarchPl
         MarchPlan pb = p;
         a.band_ty0 = band * p.nty_band;
         a.nty_band = std::min(p.nty_band, p.nty - a.band_ty0);
+        if (band == p.nbands - 1 && p.nseg_last > 0) {
+            // the short last band: its own x segments and their side planes
+            a.nseg = p.nseg_last;
+            a.seg_len = p.seg_len_last;
+            a.side = b.side ? static_cast<unsigned char*>(b.side) + p.side_off_last : nullptr;
+        }
         a.shell_lo = (inplace && band > 0) ? b.shell + (size_t(2 * (band - 1) + 1)) * part : nullptr;
         a.shell_hi = (inplace && p.nbands > 1 && band == p.nbands - 1 && py) ? b.shell : nullptr;
         // work items of the round; the grid is padded with idle workgroups to
         // a multiple of 8 (when they still fit) so that the XCD remap applies
-        a.items = a.nty_band * p.ntz * p.nseg;
+        a.items = a.nty_band * p.ntz * a.nseg;
         const int padded = (a.items + 7) / 8 * 8;
         pb.blocks = padded <= p.cap ? padded : a.items;
         pb.xcd_remap = (pb.blocks % 8 == 0) ? 1 : 0;

@@ -40,11 +40,13 @@ bool march_shape_of(int storage, int M, int variant, int nz, bool plain, MarchPl
 // least as thick as the halo (or whole).
 bool plain_shape_for_seam(int storage, int M, int ny, MarchPlan* r, int lat = 19);
 // Tiles, segments, rounds and the hazard neighbourhood of one pass of M
-// steps for at most cap co-resident workgroups.
-lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::string* why);
+// steps for at most cap co-resident workgroups (last_segments: a short last
+// band of tile rows may take x segments of its own).
+lbm_status make_plan(const lbm_config& c, int M, int cap, MarchPlan* p, std::string* why, bool last_segments = true);
 // Offsets of the work buffer's parts (off[6]) and its size; fills the plans
 // of the pass lengths the scheme runs.
-lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6], size_t* total, std::string* why);
+lbm_status layout(const lbm_config& c, int cap, MarchPlan plans[4], size_t off[6], size_t* total, std::string* why,
+                  bool last_segments = true);
 // Workgroups of the plan's kernel the device holds at once.
 int device_cap(const lbm_config& c, const MarchPlan& p);
 

@@ -90,13 +90,27 @@ def test_rounds_plan_for_large_planes():
     assert _status(_cfg(shape=(nx, 1000, 1024)))[0] == capi.LBM_OK
     assert _status(_cfg(shape=(nx, 1009, 1024)))[0] == capi.LBM_OK
     # FP64 (plain layout, 10 x 32 tiles): 103 x 32 tiles, bands of 8 tile rows
-    # (256 // 32), 13 rounds, each band's 2 M boundary rows saved; variant 1
-    # (12 x 28 tiles): 86 x 37 tiles, bands of 6 tile rows, 15 rounds
-    for variant, rounds in ((0, 13), (1, 15)):
+    # (256 // 32), 13 rounds, each band's 2 M boundary rows saved, and the side
+    # planes of one x segment; variant 1 (12 x 28 tiles): 86 x 37 tiles, bands
+    # of 6 tile rows, 15 rounds, the last of 2 rows (74 tiles) in 3 x segments
+    # of its own, whose side planes follow (and a 4 KB progress counter per
+    # tile and segment of the most numerous segmentation)
+    for variant, rounds, segs, tiles in ((0, 13, 1, 103 * 32), (1, 15, 1 + 3, 86 * 37)):
         st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024), storage=capi.LBM_F64, variant=variant))
         assert st == capi.LBM_OK
         shells = rounds * 2 * 2 * 1024 * nx * 19 * 8
-        assert shells <= wb < shells + 19 * 8 * 1024 * 1024 * 4 + (1 << 24), (variant, wb)
+        side = segs * 2 * 19 * 1024 * 1024 * 8
+        flags = (tiles * (segs - 1 if segs > 1 else 1) + 1) * 4096
+        assert shells + side + flags <= wb < shells + side + flags + (1 << 24), (variant, wb)
+    # FP64 512^3 (10 x 32 tiles): 52 x 16 tiles in bands of 16, 16, 16 and 4 tile
+    # rows; the short last band marches in 4 x segments of its own (64 tiles x 4
+    # = 256 workgroups), whose side planes (M planes of 19 per segment) follow
+    # the other bands' one segment
+    st, fb, wb = _status(_cfg(shape=(512, 512, 512), storage=capi.LBM_F64))
+    assert st == capi.LBM_OK
+    shells = 4 * 2 * 2 * 512 * 512 * 19 * 8
+    side_one = 2 * 19 * 512 * 512 * 8
+    assert shells + 5 * side_one <= wb < shells + 5 * side_one + (1 << 24), wb
     # a ragged last tile row across the periodic seam at least as thick as the halo
     assert _status(_cfg(shape=(nx, 1000, 1024), storage=capi.LBM_F64))[0] == capi.LBM_OK
     # 1009 rows: 10-row tiles leave a last row of 9; 12-row ones (variant 1) a row of

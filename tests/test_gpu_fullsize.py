@@ -152,6 +152,13 @@ BANDED_CASES = [
     ((5, 296, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
     # a last row of 16-row tiles thinner than the halo (305 = 19 x 16 + 1): 32 x 32 plain tiles for two steps
     ((4, 305, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    # a short last band (1 of 17 tile rows, 16 tiles) marching in x segments of
+    # its own (10 of 4 planes; the other band in one), across the x wrap
+    ((40, 272, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    # the same with walls in x and a lid (last band 3 x 17 tiles, 5 segments)
+    ((24, 280, 1030), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),
+    # and in the plain layout (odd nz; last band 3 x 16 tiles, 5 segments)
+    ((20, 304, 1001), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
 ]
 _NAMES = {PERIODIC: "periodic", WALL: "wall", MOVING_WALL: "moving"}
 
@@ -200,6 +207,9 @@ FP64_BANDED_CASES = [
     # periodic seam its rows above share waves with its own rows (the per-lane
     # source choice)
     ((4, 39, 3640), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    # a short last band in x segments of its own (10 x 32: 4 of 20 tile rows,
+    # 128 tiles, 2 segments; 12 x 28: 3 of 17 rows, 108 tiles, 2 segments)
+    ((24, 200, 1000), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
 ]
 
 
@@ -278,7 +288,7 @@ def test_rounds_with_force_match_two_array_bitwise(storage):
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 @pytest.mark.parametrize("case,force", [(0, False), (1, False), (3, False), (4, False), (5, False), (6, False),
-                                        (1, True), (4, True)])
+                                        (7, False), (8, True), (9, False), (1, True), (4, True)])
 def test_rounds_16bit_in_place_matches_out_of_place(storage, case, force):
     # 16-bit offset storage in rounds: the saved band boundary rows are raw
     # 16-bit codes.  The merged pass rounds to 16 bits once per two steps (the

@@ -49,13 +49,20 @@ def source_digest(names=MARCH_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
+# Extra hipcc flags per source.  The FP64 marching kernel that loads two
+# planes ahead runs its plane iteration as two inlined bodies (one per load
+# buffer); at the default inlining threshold the second stays a call and the
+# load buffers go to scratch memory.
+EXTRA_FLAGS = {"march_f64.hip": ["-mllvm", "-inline-threshold=100000"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src, resource_usage):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     if resource_usage:

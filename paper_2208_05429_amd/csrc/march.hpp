@@ -158,7 +158,7 @@ __device__ __forceinline__ void deposit(R (&acc)[LT::Q], R (&nxt)[nxp<LT>()], co
     });
 }
 
-template <class LT, int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS>
+template <class LT, int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, int PF = 1>
 __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 {
     constexpr int QL = LT::Q;                 // velocities
@@ -177,6 +177,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     constexpr int NB1 = (M == 1) ? 2 : 1;  // a single exchange level is double-buffered
     constexpr uint32_t CXP = mask_cx<LT>(1), CXM = mask_cx<LT>(-1);
     static_assert(M >= 1 && M <= 3, "one to three merged steps");
+    static_assert(PF == 1 || PF == 2, "loads run one or two planes ahead");
 
     __shared__ R X1[NB1][NYZ * NC];
     __shared__ R X2[(M >= 2) ? NYZ * NC2 : 1];
@@ -291,14 +292,14 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     auto present = [&](int p) -> bool { return !wallx || (p >= 0 && p < g.nx); };
 
     // ---- pipeline registers ----
-    T Lr[K][QL];
-    R Fl1[K][3], Fl2[K][3], Fl3[K3][3];
+    T Lr[PF][K][QL];  // raw loads, PF planes in flight
+    R Fl1[PF][K][3], Fl2[K][3], Fl3[K3][3];
     R acc1[K][QL], nxt1[K][NXP], acc2[K][QL], nxt2[K][NXP], acc3[K3][QL], nxt3[K3][NXP];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
         for (int q = 0; q < QL; ++q) {
-            Lr[k][q] = T(0);
+            for (int b = 0; b < PF; ++b) Lr[b][k][q] = T(0);
             acc1[k][q] = R(0);
             acc2[k][q] = R(0);
             if constexpr (M == 3) acc3[k][q] = R(0);
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Fl1[k][c] = R(0);
+            for (int b = 0; b < PF; ++b) Fl1[b][k][c] = R(0);
             Fl2[k][c] = R(0);
             if constexpr (M == 3) Fl3[k][c] = R(0);
         }
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     // absent (beyond a wall) or past the end of the march gets an empty buffer
     // range, so the hardware returns zeros without touching memory.  Uniform
     // issue keeps the compiler's count of outstanding memory operations exact.
-    auto issue_load_slot = [&](int xp, bool wanted, int k) {
+    auto issue_load_slot = [&](int xp, bool wanted, int k, T (&L)[QL], R (&Fb)[3]) {
         const bool live = wanted && present(xp);
         const bool from_side = a.inplace && xp >= e && has_next;
         const int px = wrapi(xp, g.nx);
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         if (!ROUNDS || !(shell_lo || shell_hi) || from_side) {  // (the side planes hold every row at time t)
 #pragma unroll
             for (int q = 0; q < QL; ++q) {
-                Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), loff[k]);
+                L[q] = Buf<T>::ld(make_rsrc(bq, range), loff[k]);
                 bq += qstride;
             }
         } else {
@@ -383,19 +384,19 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             if (!any_lo && !any_hi) {
 #pragma unroll
                 for (int q = 0; q < QL; ++q) {
-                    Lr[k][q] = Buf<T>::ld(make_rsrc(bq, range), lf);
+                    L[q] = Buf<T>::ld(make_rsrc(bq, range), lf);
                     bq += qstride;
                 }
             } else if (!any_lat && !any_hi) {
 #pragma unroll
                 for (int q = 0; q < QL; ++q) {
-                    Lr[k][q] = Buf<T>::ld(make_rsrc(blo, srange), olo);
+                    L[q] = Buf<T>::ld(make_rsrc(blo, srange), olo);
                     blo += ss;
                 }
             } else if (!any_lat && !any_lo) {
 #pragma unroll
                 for (int q = 0; q < QL; ++q) {
-                    Lr[k][q] = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
+                    L[q] = Buf<T>::ld(make_rsrc(bhi, srange), ohi);
                     bhi += ss;
                 }
             } else {
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                 const uintptr_t own = in_lo ? ulo + olo : (in_hi ? uhi + ohi : ula + (lf == kOffNone ? 0u : lf));
                 const uintptr_t step = (in_lo || in_hi) ? dlo : dla;
 #pragma unroll
-                for (int q = 0; q < QL; ++q) Lr[k][q] = *reinterpret_cast<GT*>(own + uintptr_t(q) * step);
+                for (int q = 0; q < QL; ++q) L[q] = *reinterpret_cast<GT*>(own + uintptr_t(q) * step);
             }
         }
         if constexpr (FORCE) {
@@ -419,14 +420,14 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             const R* bc = F + (long long)px * PL;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Fl1[k][c] = Buf<R>::ld(make_rsrc(bc, rangeR), loffR[k]);
+                Fb[c] = Buf<R>::ld(make_rsrc(bc, rangeR), loffR[k]);
                 bc += N;
             }
         }
     };
-    auto issue_load = [&](int xp, bool wanted) {
+    auto issue_load = [&](int xp, bool wanted, T (&L)[K][QL], R (&Fb)[K][3]) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) issue_load_slot(xp, wanted, k);
+        for (int k = 0; k < K; ++k) issue_load_slot(xp, wanted, k, L[k], Fb[k]);
     };
 
     // Hazard check.  Every wave watches the progress counters itself, one per
@@ -464,7 +465,8 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
     }
     // plane r is stored in iteration i = r - s + 2M + 1; every work item whose
     // halo covers it loads it in its iteration r - s' + M, i.e. has published
-    // a load front >= r - s' + M + 1
+    // a load front >= r - s' + M + 1 (with loads two planes ahead, one
+    // iteration earlier still: the same bound holds)
     auto poll_need = [&](int i, int r) -> int {
         if (fkind == 1) return i - M;
         if (fkind == 2 && r >= e - M) return r - e + M + 1;
@@ -498,7 +500,8 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
     // Pipeline of one iteration (load front at plane xl):
     //   A  step-1 collide of plane xl on the tile plus M halo cells, then at
-    //      once the loads of plane xl+1 for the same column;
+    //      once the loads of plane xl+PF for the same column (PF = 2: two
+    //      register buffers of loads, used in turn);
     //   D  receive of the last step from the exchange filled one iteration
     //      earlier: completes plane xl-M-1 (time t+M), stored in place after
     //      the hazard check;
@@ -523,17 +526,21 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         }
     if constexpr (WALLS) __syncthreads();  // the wall-term table is complete
     const int total = (e - s) + 2 * M + 1;
-    issue_load(s - M, true);
+    // prologue: the first PF planes; iteration i consumes buffer i % PF and
+    // refills it with plane xl + PF (planes up to e - 1 + M are wanted)
+#pragma unroll
+    for (int b = 0; b < PF; ++b) issue_load(s - M + b, s - M + b <= e - 1 + M, Lr[b], Fl1[b]);
     int seen = poll_issue();
-    for (int i = 0; i < total; ++i) {
+    auto iteration = [&](auto pbc, int i) {
+        constexpr int pb = decltype(pbc)::value;
         const int xl = s - M + i;
         R* X1w = X1[(M == 1) ? (i & 1) : 0];        // filled by this iteration's step-1 collide
         R* X1r = X1[(M == 1) ? ((i + 1) & 1) : 0];  // (M = 1) filled one iteration earlier
         const int r_out = xl - M - 1;
         const bool storing = r_out >= s && r_out < e;
-        const bool next_wanted = xl + 1 <= e - 1 + M;
+        const bool next_wanted = xl + PF <= e - 1 + M;
 
-        // ---- A: step-1 collide of plane xl, then the loads of plane xl+1 ----
+        // ---- A: step-1 collide of plane xl, then the loads of plane xl+PF ----
         R Fs[K][3];
         const bool pres = present(xl);
         const uint32_t xmc = xm(xl);
@@ -541,13 +548,13 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         for (int k = 0; k < K; ++k) {
             if constexpr (FORCE) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[k][c];
+                for (int c = 0; c < 3; ++c) Fs[k][c] = Fl1[pb][k][c];
             }
             if (pres && rad[k] <= M && gofs[k] >= 0) {
                 R v[QL];
 #pragma unroll
-                for (int q = 0; q < QL; ++q) v[q] = Cd::dec(Lr[k][q]);
-                LT::template collide<R, FORCE>(v, omega, Fl1[k][0], Fl1[k][1], Fl1[k][2]);
+                for (int q = 0; q < QL; ++q) v[q] = Cd::dec(Lr[pb][k][q]);
+                LT::template collide<R, FORCE>(v, omega, Fl1[pb][k][0], Fl1[pb][k][1], Fl1[pb][k][2]);
                 const int c = tid + k * NT;
                 sfor<0, QL>([&](auto qc) {
                     constexpr int q = decltype(qc)::value;
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
                 o1[k][1] = v[1];
                 o1[k][2] = v[XP];
             }
-            issue_load_slot(xl + 1, next_wanted, k);
+            issue_load_slot(xl + PF, next_wanted, k, Lr[pb][k], Fl1[pb][k]);
         }
 
         // ---- D: last-step receive, hazard check, in-place stores ----
@@ -670,27 +677,33 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
             seen = poll_issue();
             __syncthreads();
         }
+    };
+    for (int i = 0; i < total; i += PF) {
+        iteration(std::integral_constant<int, 0>{}, i);
+        if constexpr (PF == 2) {
+            if (i + 1 < total) iteration(std::integral_constant<int, 1>{}, i + 1);
+        }
     }
 }
 
 // Launch of one compiled shape.  Cooperative launch guarantees co-residency
 // of all work items (required by the progress-counter protocol).
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, class LT = D3Q19>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, class LT = D3Q19, int PF = 1>
 hipError_t launch_march_shape(const MarchPlan& p, const MarchArgs& a, hipStream_t st)
 {
-    auto kern = k_march<LT, S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>;
+    auto kern = k_march<LT, S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS, PF>;
     MarchArgs arg = a;
     void* params[] = {&arg};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(p.blocks), dim3(NT), params, 0, st);
 }
 
-template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, class LT = D3Q19>
+template <int S, int M, int TY, int TZ, int NT, bool WALLS, bool FORCE, bool ROUNDS, class LT = D3Q19, int PF = 1>
 int max_blocks_shape()
 {
     int dev = 0, per_cu = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<LT, S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS>, NT,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march<LT, S, M, TY, TZ, NT, WALLS, FORCE, ROUNDS, PF>, NT,
                                                      0) != hipSuccess)
         return 0;
     return per_cu * cus;

@@ -8,11 +8,14 @@
 
 namespace lbm {
 
-template <int S, int M, int TY, int TZ, int NT, bool ALLOW_FORCE>
+// A plain-layout shape (march.hpp).  PF is how many planes ahead the loads
+// run; walls and a body force use PF = 1 (their extra registers leave no room
+// for a second plane of loads).
+template <int S, int M, int TY, int TZ, int NT, bool ALLOW_FORCE, int PF = 1>
 struct Shape {
     static bool match(const MarchPlan& p)
     {
-        return p.pr == 0 && p.pf == 1 && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
+        return p.pr == 0 && p.pf == PF && p.M == M && p.TY == TY && p.TZ == TZ && p.NT == NT;
     }
     // FP64 always runs the build with the band edge code; the other storages
     // only for planes that run in rounds
@@ -27,7 +30,7 @@ struct Shape {
             if (force) return hipErrorInvalidValue;
         }
         return walls ? launch_march_shape<S, M, TY, TZ, NT, true, false, R>(p, a, s)
-                     : launch_march_shape<S, M, TY, TZ, NT, false, false, R>(p, a, s);
+                     : launch_march_shape<S, M, TY, TZ, NT, false, false, R, D3Q19, PF>(p, a, s);
     }
     template <bool R>
     static int max_blocks_r(bool walls, bool force)
@@ -40,7 +43,7 @@ struct Shape {
             if (force) return 0;
         }
         return walls ? max_blocks_shape<S, M, TY, TZ, NT, true, false, R>()
-                     : max_blocks_shape<S, M, TY, TZ, NT, false, false, R>();
+                     : max_blocks_shape<S, M, TY, TZ, NT, false, false, R, D3Q19, PF>();
     }
     static hipError_t launch(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
     {
@@ -126,7 +129,8 @@ struct ShapeEntry {
 // 1024-wide plane takes 32 tiles per row: eight rows fill 256 workgroups),
 // 12 x 28 as variant 1.
 constexpr ShapeEntry kShapesF64[] = {{2, 10, 32, 512, 0, 1}, {1, 12, 34, 512, 0, 1},
-                                     {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}};
+                                     {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1},
+                                     {2, 10, 32, 512, 0, 2}, {1, 12, 34, 512, 0, 2}};
 constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}, {2, 16, 64, 512, 0, 1},
                                      {1, 16, 64, 512, 0, 1}, {2, 32, 32, 512, 1, 1}, {1, 32, 32, 512, 1, 1},
                                      {2, 32, 32, 512, 0, 1}, {1, 32, 32, 512, 0, 1}, {2, 16, 64, 512, 1, 2},

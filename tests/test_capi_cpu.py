@@ -95,7 +95,8 @@ def test_rounds_plan_for_large_planes():
     # of 6 tile rows, 15 rounds, the last of 2 rows (74 tiles) in 3 x segments
     # of its own, whose side planes follow (and a 4 KB progress counter per
     # tile and segment of the most numerous segmentation)
-    for variant, rounds, segs, tiles in ((0, 13, 1, 103 * 32), (1, 15, 1 + 3, 86 * 37)):
+    # (variant 2: the 10 x 32 tile with loads two planes ahead, the same plan)
+    for variant, rounds, segs, tiles in ((0, 13, 1, 103 * 32), (1, 15, 1 + 3, 86 * 37), (2, 13, 1, 103 * 32)):
         st, fb, wb = _status(_cfg(shape=(nx, 1024, 1024), storage=capi.LBM_F64, variant=variant))
         assert st == capi.LBM_OK
         shells = rounds * 2 * 2 * 1024 * nx * 19 * 8

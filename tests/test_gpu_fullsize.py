@@ -213,7 +213,7 @@ FP64_BANDED_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("case", range(len(FP64_BANDED_CASES)))
 def test_rounds_fp64_match_two_array_bitwise(case, variant):
     shape, faces, wall_u = FP64_BANDED_CASES[case]

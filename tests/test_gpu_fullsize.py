@@ -2,7 +2,8 @@
 times, on sampled cells.
 
 After n steps a cell depends only on the initial cells within Chebyshev
-distance n (a D3Q19 population moves at most one cell per axis per step).
+distance n (a population of D3Q15, D3Q19 or D3Q27 moves at most one cell per
+axis per step).
 For each sampled cell the FP64 oracle runs on the (2n+3)^3 neighbourhood of
 the initial field: periodic axes are wrapped into the box; where the box
 meets a wall of the domain it is cut there and the wall kept, and every other
@@ -13,7 +14,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import MOVING_WALL, PERIODIC, WALL, Oracle
+from oracle import MOVING_WALL, PERIODIC, WALL, Oracle, OracleQ
 from paper_2208_05429_amd import workloads as wl
 from paper_2208_05429_amd.lattice import Lattice
 
@@ -38,9 +39,10 @@ def cone_box(shape, faces, center, n):
     return idx, tuple(box_faces), tuple(pos)
 
 
-def oracle_center(rho0, u0, shape, faces, wall_u, tau, center, n):
+def oracle_center(rho0, u0, shape, faces, wall_u, tau, center, n, q=19):
     """u0: the full initial velocity array, or a function of the box's index
-    arrays (ix, iy, iz) returning it on that box."""
+    arrays (ix, iy, iz) returning it on that box; q: the velocity set (the
+    D3Q15/D3Q27 oracle for 15 and 27)."""
     idx, bfaces, pos = cone_box(shape, faces, center, n)
     ix = np.ix_(*idx)
     r = None if rho0 is None else np.ascontiguousarray(rho0[ix])
@@ -49,18 +51,19 @@ def oracle_center(rho0, u0, shape, faces, wall_u, tau, center, n):
     else:
         u = None if u0 is None else np.ascontiguousarray(np.stack([u0[c][ix] for c in range(3)]))
     bshape = tuple(len(i) for i in idx)
-    o = Oracle(bshape, tau, faces=bfaces, wall_u=wall_u)
+    o = Oracle(bshape, tau, faces=bfaces, wall_u=wall_u) if q == 19 else OracleQ(bshape, tau, q, faces=bfaces,
+                                                                                   wall_u=wall_u)
     f = o.run(o.init(r, u), n)
     return f[(slice(None),) + pos]
 
 
-def gpu_cells(lat, cells):
+def gpu_cells(lat, cells, q=19):
     f = lat.f
     out = []
     for c in cells:
         out.append(f[(slice(None),) + tuple(c)].to(torch.float64).cpu().numpy())
     from paper_2208_05429_amd.lattice import lattice_weights
-    return np.array(out) + lattice_weights()[None, :]
+    return np.array(out) + lattice_weights(q)[None, :]
 
 
 def test_tgv512_fp32_merged_sampled_cells():
@@ -363,7 +366,8 @@ def test_tgv1024_fp32_merged_rounds_sampled_cells():
 def test_tgv1024_fp64_merged_rounds_sampled_cells():
     # 1024^3 in FP64: 163 GB of distributions, which fit the 288 GB of HBM only
     # as a single copy (two arrays would need 326 GB); 13 rounds of bands of
-    # eight 10-row tile rows per merged pass, a ragged last tile row across the seam
+    # eight 10-row tile rows per merged pass (the last band 7 rows), a ragged
+    # last tile row (1020-1023) across the seam
     cfg = wl.TGV_1024
     shape, tau, n = cfg["shape"], cfg["tau"], 4
     ph = wl.random_phases(cfg["phase_seed"])
@@ -376,10 +380,12 @@ def test_tgv1024_fp64_merged_rounds_sampled_cells():
     lat.step(n)
     torch.cuda.synchronize()
     s1 = lat.sums()
-    # band seams (rows 71/72, 143/144, 1007/1008), the ragged last tile row
-    # (1020-1023) and its periodic seam, tile seams in z (28-column tiles), the x wrap
-    cells = [(0, 71, 0), (1, 72, 27), (1023, 143, 28), (512, 144, 1023), (7, 1007, 500), (100, 1008, 511),
-             (5, 1019, 3), (3, 1020, 55), (1023, 1023, 1), (0, 0, 1022)] + wl.sample_cells(shape, 8, 12)
+    # band seams (rows 79/80, 159/160, 959/960), the ragged last tile row
+    # (1020-1023) and its periodic seam, tile seams in z (32-column tiles), the
+    # x wrap; (rows 71/72 and 143/144: the band seams of 12 x 28 tiles)
+    cells = [(0, 79, 0), (1, 80, 31), (1023, 159, 32), (512, 160, 1023), (7, 959, 500), (100, 960, 511),
+             (5, 1019, 3), (3, 1020, 63), (1023, 1023, 1), (0, 0, 1022), (0, 71, 0), (1, 72, 27),
+             (1023, 143, 28)] + wl.sample_cells(shape, 8, 12)
     got = gpu_cells(lat, cells)
     ufn = lambda ix, iy, iz: wl.taylor_green_3d_at(shape, cfg["u0"], ph, ix, iy, iz)  # noqa: E731
     faces = (PERIODIC,) * 6

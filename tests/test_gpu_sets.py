@@ -263,3 +263,73 @@ def test_set_tile_variants_equal_two_array_bitwise(q, variant, case):
         lat.close()
         r.close()
     ref.close()
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_sets_512_cubed_fp32_merged_sampled_cells(q):
+    # The sets at the size they are measured at: 512^3 periodic Taylor-Green +
+    # noise, FP32, two merged steps per pass, in the bench's launch
+    # configuration (D3Q15: one round of 16 x 64 pair-and-ring tiles; D3Q27:
+    # two rounds of 16 x 32 tiles, two columns per thread).  Sampled cells
+    # against the set's oracle run on each cell's dependency cone (exact by
+    # the locality of streaming, pinned on the CPU in test_cone_oracle.py).
+    from tests.test_gpu_fullsize import gpu_cells, oracle_center
+    cfg = wl.TGV_512
+    shape, tau, n = cfg["shape"], cfg["tau"], 4
+    print(f"[gpu] D3Q{q} 512^3 f32 swap2 sampled cells, {n} steps", flush=True)
+    _, u0 = wl.tgv_512_fields(shape)
+    lat = Lattice(shape, tau, "f32", "swap2", u0=torch.from_numpy(u0), velocities=q)
+    s0 = lat.sums()
+    lat.step(n)
+    torch.cuda.synchronize()
+    s1 = lat.sums()
+    # tile seams (y: 16 rows; z: 64 or 32 columns), the D3Q27 band seam (rows
+    # 255/256), corners and the x wrap
+    cells = [(0, 255, 63), (1, 256, 64), (511, 15, 31), (256, 16, 32), (0, 0, 0), (511, 511, 511),
+             (3, 511, 0)] + wl.sample_cells(shape, 10, 13)
+    got = gpu_cells(lat, cells, q)
+    worst = 0.0
+    for c, g in zip(cells, got):
+        ref = oracle_center(None, u0, shape, (PERIODIC,) * 6, (0.0, 0.0, 0.0), tau, c, n, q=q)
+        err = float(np.abs(g - ref).max())
+        worst = max(worst, err)
+        assert err <= 2e-7, (c, err)  # FP32 rounding of the offsets over a few steps
+    print(f"D3Q{q} 512^3 sampled cells: max abs error {worst:.2e}")
+    assert abs(s1[0] - s0[0]) <= 1e-9 * s0[0]
+    assert np.abs(s1[1:] - s0[1:]).max() <= 1e-9 * s0[0]
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_sets_1024_cubed_fp32_merged_rounds_sampled_cells(q):
+    # 1024^3 single copy in rounds (D3Q15: 64 GB, four bands of 16 rows of
+    # 16 x 64 tiles; D3Q27: 116 GB, eight bands of 8 rows of 16 x 32 tiles),
+    # the random-phase Taylor-Green field built on the device; sampled cells at
+    # the band seams, the x wrap and at random against the set's cone oracle
+    from tests.test_gpu_fullsize import gpu_cells, oracle_center
+    cfg = wl.TGV_1024
+    shape, tau, n = cfg["shape"], cfg["tau"], 4
+    ph = wl.random_phases(cfg["phase_seed"])
+    print(f"[gpu] D3Q{q} 1024^3 f32 swap2 rounds, {n} steps", flush=True)
+    u0 = wl.taylor_green_3d_device(shape, cfg["u0"], ph, "cuda")
+    lat = Lattice(shape, tau, "f32", "swap2", u0=u0, velocities=q)
+    del u0
+    torch.cuda.empty_cache()
+    s0 = lat.sums()
+    lat.step(n)
+    torch.cuda.synchronize()
+    s1 = lat.sums()
+    cells = [(0, 127, 0), (1, 128, 31), (1023, 255, 32), (512, 256, 63), (7, 511, 64), (100, 512, 1023),
+             (9, 767, 500), (11, 768, 511), (1023, 1023, 1), (0, 0, 1022)] + wl.sample_cells(shape, 8, 14)
+    got = gpu_cells(lat, cells, q)
+    ufn = lambda ix, iy, iz: wl.taylor_green_3d_at(shape, cfg["u0"], ph, ix, iy, iz)  # noqa: E731
+    for c, g in zip(cells, got):
+        ref = oracle_center(None, ufn, shape, (PERIODIC,) * 6, (0.0, 0.0, 0.0), tau, c, n, q=q)
+        assert np.abs(g - ref).max() <= 2e-7, c
+    assert abs(s1[0] - s0[0]) <= 1e-9 * s0[0]
+    assert np.abs(s1[1:] - s0[1:]).max() <= 1e-9 * s0[0]
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()

@@ -23,7 +23,8 @@ constexpr SetShapes kSetShapes[] = {
     {15, ST_F32, 1, {2, 16, 64, 512, 0, 1}, {1, 16, 64, 512, 0, 1}},  // three columns per thread
     {15, ST_F32, 2, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},
     {15, ST_F32, 3, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
-    {15, ST_F64, 0, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
+    {15, ST_F64, 0, {2, 10, 32, 512, 0, 1}, {1, 12, 34, 512, 0, 1}},  // whole cache-line rows (as D3Q19 FP64)
+    {15, ST_F64, 1, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
     {27, ST_F32, 0, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},  // two columns per thread
     {27, ST_F32, 1, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
     {27, ST_F64, 0, {2, 8, 24, 384, 0, 1}, {1, 10, 26, 384, 0, 1}},

@@ -265,23 +265,25 @@ def test_set_tile_variants_equal_two_array_bitwise(q, variant, case):
     ref.close()
 
 
+@pytest.mark.parametrize("q", [15, 27])
 @pytest.mark.parametrize("case", [0, 1, 2, 3, 4, 5])
-def test_d3q15_fp64_tile_variants_equal_two_array_bitwise(case):
-    # D3Q15 in FP64, both tiles (variant 0: 10 x 32; variant 1: 12 x 28), on
-    # ragged and walled lattices and, for case 5, a plane that runs in rounds
-    # (264 x 1000: 27 x 32 tiles of 10 x 32 in bands of 8, 8, 8 and 3 tile
-    # rows, the last in 2 x segments of its own; 22 x 36 of 12 x 28 in bands
-    # of 7, 7, 7 and 1, the last in 6 segments)
+def test_fp64_tile_variants_equal_two_array_bitwise(q, case):
+    # FP64, both tiles of each set (D3Q15 variant 0: 10 x 32, variant 1:
+    # 12 x 28; D3Q27 variant 0: 8 x 32, variant 1: 8 x 24), on ragged and
+    # walled lattices and, for case 5, a plane that runs in rounds (264 x 1000:
+    # D3Q15 10 x 32 in bands of 8, 8, 8 and 3 tile rows, the last in 2 x
+    # segments of its own, 12 x 28 in bands of 7, 7, 7 and 1, the last in 6
+    # segments; D3Q27 8 x 32 in bands of 8 ending on one row in 6 segments)
     shape, faces, wall_u = (CASES[case] if case < 5 else ((24, 264, 1000), (PERIODIC,) * 6, (0.0, 0.0, 0.0)))
     rho0, u0 = _init(shape, 760 + case)
     names = [NAMES[f] for f in faces]
     ref = Lattice(shape, 0.7, "f64", "two_array", names, wall_u, None, torch.as_tensor(rho0), torch.as_tensor(u0),
-                  velocities=15)
+                  velocities=q)
     for variant in (0, 1):
-        print(f"[gpu] D3Q15 f64 variant {variant} {shape}", flush=True)
+        print(f"[gpu] D3Q{q} f64 variant {variant} {shape}", flush=True)
         for scheme in ("swap2", "swap1"):
-            lat = Lattice(shape, 0.7, "f64", scheme, names, wall_u, f=ref.f.clone(), variant=variant, velocities=15)
-            r = Lattice(shape, 0.7, "f64", "two_array", names, wall_u, f=ref.f.clone(), velocities=15)
+            lat = Lattice(shape, 0.7, "f64", scheme, names, wall_u, f=ref.f.clone(), variant=variant, velocities=q)
+            r = Lattice(shape, 0.7, "f64", "two_array", names, wall_u, f=ref.f.clone(), velocities=q)
             lat.step(5)
             r.step(5)
             torch.cuda.synchronize()

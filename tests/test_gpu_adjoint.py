@@ -122,7 +122,7 @@ def test_force_gradient_matches_central_differences_fp64():
 # Two merged reverse steps (one pass, f_{t+1} recomputed on chip) against two
 # single reverse steps of the oracle.  Shapes span several tiles (FP32: the
 # fewest tiles of 12x28, 10x32 and 16x16: 12x28 for the first four cases,
-# 10x32 for the last; FP64: 8x8) with ragged last tiles and several x segments.
+# 10x32 for the last; FP64: 8x16) with ragged last tiles and several x segments.
 MERGED_CASES = [
     ((40, 21, 19), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
     ((24, 18, 37), (PERIODIC,) * 6, (0.0, 0.0, 0.0), True),

@@ -454,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         } else {
             yy = wrapi(yy, a.nty);
         }
-        if (yy < a.band_ty0 || yy >= a.band_ty0 + a.nty_band) fkind = 0;  // not in this round
+        if (yy < a.band_ty0 || yy >= a.band_ty0 + a.nty_band) fkind = 0;  // a tile row outside the band being marched
         if (g.wall[2]) {
             if (zz < 0 || zz >= a.ntz) fkind = 0;
         } else {

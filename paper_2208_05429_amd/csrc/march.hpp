@@ -487,13 +487,16 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
 
     // Stores, like loads, are issued every iteration by every slot; lanes that
     // do not own a finished interior column carry an out-of-range offset and a
-    // plane that is not stored this iteration gets an empty range.
-    auto store = [&](const R (&out)[QL], int k, int r, bool live) {
+    // plane that is not stored this iteration gets an empty range.  The slots
+    // share each direction's buffer descriptor.
+    auto store_all = [&](const R (&out)[K][QL], int r, bool live) {
         const T* bq = fo + (long long)(live ? r : 0) * PL;
         const uint32_t range = live ? plane_bytes : 0u;
 #pragma unroll
         for (int q = 0; q < QL; ++q) {
-            Buf<T>::st(Cd::enc(out[q]), make_rsrc(bq, range), soff[k]);
+            const auto rs = make_rsrc(bq, range);
+#pragma unroll
+            for (int k = 0; k < K; ++k) Buf<T>::st(Cd::enc(out[k][q]), rs, soff[k]);
             bq += N;
         }
     };
@@ -569,32 +572,44 @@ __global__ __launch_bounds__(NT) void k_march(MarchArgs a)
         }
 
         // ---- D: last-step receive, hazard check, in-place stores ----
+        // (complete and deposit only read the exchange, so every slot
+        // completes, then all store together, then all deposit)
         if (storing) poll_finish(seen, i, r_out);
         {
             const int p = xl - M;  // plane collided by the last step one iteration ago
             const uint32_t xbd = xb(p - 1), xbn = xb(p);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const bool act = rad[k] == 0 && gofs[k] >= 0;
-                if constexpr (M == 3) {
-                    if (act) complete<R, WALLS, LT>(acc3[k], X3, NC3, ci3[k], WZ3, o3[k][1], byz[k] | xbd);
-                    store(acc3[k], k, r_out, storing);
-                    if (act)
+                if (rad[k] == 0 && gofs[k] >= 0) {
+                    if constexpr (M == 3) {
+                        complete<R, WALLS, LT>(acc3[k], X3, NC3, ci3[k], WZ3, o3[k][1], byz[k] | xbd);
+                    } else if constexpr (M == 2) {
+                        complete<R, WALLS, LT>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
+                    } else {
+                        complete<R, WALLS, LT>(acc1[k], X1r, NC, tid + k * NT, WZ, o1p[k][1], byz[k] | xbd);
+                    }
+                }
+            }
+            if constexpr (M == 3)
+                store_all(acc3, r_out, storing);
+            else if constexpr (M == 2)
+                store_all(acc2, r_out, storing);
+            else
+                store_all(acc1, r_out, storing);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (rad[k] == 0 && gofs[k] >= 0) {
+                    if constexpr (M == 3) {
                         deposit<R, WALLS, LT>(acc3[k], nxt3[k], X3, NC3, ci3[k], WZ3, o3[k][0], o3[k][1], o3[k][2],
-                                          byz[k] | xbn);
-                } else if constexpr (M == 2) {
-                    if (act) complete<R, WALLS, LT>(acc2[k], X2, NC2, ci2[k], WZ2, o2[k][1], byz[k] | xbd);
-                    store(acc2[k], k, r_out, storing);
-                    if (act)
+                                              byz[k] | xbn);
+                    } else if constexpr (M == 2) {
                         deposit<R, WALLS, LT>(acc2[k], nxt2[k], X2, NC2, ci2[k], WZ2, o2[k][0], o2[k][1], o2[k][2],
-                                          byz[k] | xbn);
-                } else {
-                    const int c = tid + k * NT;
-                    if (act) complete<R, WALLS, LT>(acc1[k], X1r, NC, c, WZ, o1p[k][1], byz[k] | xbd);
-                    store(acc1[k], k, r_out, storing);
-                    if (act)
+                                              byz[k] | xbn);
+                    } else {
+                        const int c = tid + k * NT;
                         deposit<R, WALLS, LT>(acc1[k], nxt1[k], X1r, NC, c, WZ, o1p[k][0], o1p[k][1], o1p[k][2],
-                                          byz[k] | xbn);
+                                              byz[k] | xbn);
+                    }
                 }
             }
         }

@@ -95,7 +95,9 @@ typedef struct {
                            at most one LBM_MOVING_WALL */
     double wall_u[3];   /* velocity of the moving-wall face (ignored without one) */
     int32_t use_force;  /* 1: a body-force density field F (3N, double for LBM_F64, float otherwise) */
-    int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes */
+    int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes
+                           (e.g. D3Q19 FP64: 0 = 10x32 tiles, 1 = 12x28, 2 = 10x32 with loads two planes
+                           ahead); LBM_EUNSUPPORTED for a value with no compiled shape */
     int32_t velocities; /* velocity set: 0 or 19 = D3Q19 (the paper's); 15 = D3Q15, 27 = D3Q27 (Sec. 4.1 names
                            both as sets the two-step rule holds for): every storage (16-bit: the default
                            tiles), LBM_TWO_ARRAY, LBM_SWAP1 and LBM_SWAP2 (large planes in rounds), the adjoint;
@@ -111,7 +113,8 @@ typedef struct {
  * NULL; returns the status lbm_init would return for the configuration.  In-place schemes march y-z tiles with one workgroup
  * each; a plane with more tiles than the device holds workgroups at once runs
  * in rounds over bands of tile rows, whose boundary rows the work buffer then
- * also holds (across a periodic y axis a ragged last tile row then takes the
+ * also holds, with the saved planes of a short last band's own x segments
+ * (across a periodic y axis a ragged last tile row then takes the
  * one-column-per-thread layout, with another tile height where the row would
  * be thinner than the halo).  LBM_EUNSUPPORTED, with the reason, where that is
  * not built: rounds across a periodic y axis whose last tile row is thinner

@@ -160,7 +160,7 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def adjoint_ratio(shape, steps, checkpoint, reps=3, scheme="swap2", merged=True):
+def adjoint_ratio(shape, steps, checkpoint, reps=3, scheme="swap2", merged=True, variant=0):
     """Backward (recompute + merged adjoint) time per step over merged forward
     time per step, for L = sum |u_T - u*|^2 on a channel (periodic x, walls in
     y and z, tau 0.8) under a per-cell force N(0, 1e-12) (seed 1); u* from a
@@ -179,9 +179,9 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3, scheme="swap2", merged=True)
     lat.step(steps)
     _, ut, _, _ = lat.macroscopic(want=("u",))
     lat.close()
-    lat = Lattice(shape, 0.8, "f32", scheme, faces, force=F, f=f0.clone())
+    lat = Lattice(shape, 0.8, "f32", scheme, faces, force=F, f=f0.clone(), variant=variant)
     spec = dict(shape=shape, tau=0.8, storage="f32", faces=faces, steps=steps, checkpoint=checkpoint, merged=merged,
-                scheme=scheme)
+                scheme=scheme, variant=variant)
     fwd, bwd, ckf = [], [], []
     for r in range(reps + 1):
         lat.f.copy_(f0)
@@ -230,7 +230,7 @@ def adjoint_ratio(shape, steps, checkpoint, reps=3, scheme="swap2", merged=True)
     lat.close()
     fw, bw, cf = float(np.median(fwd)) / steps, float(np.median(bwd)) / steps, float(np.median(ckf)) / steps
     ka, kf = a0.elapsed_time(a1) / (kk * n), m0.elapsed_time(m1) / (kk * n)
-    return {"shape": list(shape), "steps": steps, "checkpoint": checkpoint, "scheme": scheme,
+    return {"shape": list(shape), "steps": steps, "checkpoint": checkpoint, "scheme": scheme, "variant": variant,
             "reverse_steps_per_call": 2 if merged else 1, "forward_ms_per_step": round(fw, 5),
             "backward_ms_per_step": round(bw, 5), "ratio": round(bw / fw, 3),
             "checkpointing_forward_ms_per_step": round(cf, 5),
@@ -504,9 +504,13 @@ def main():
         # of each plane: the plain two-array scheme (forward and recompute)
         # with single reverse steps is the faster configuration
         wk2 = adjoint_ratio((128, 64, 64), 200, 20, scheme="two_array", merged=False)
-        best_fw = min(wk["forward_ms_per_step"], wk2["forward_ms_per_step"])
-        best_bw = min(wk["backward_ms_per_step"], wk2["backward_ms_per_step"])
+        # the merged scheme on the 16 x 16 tiles of kernel variant 5 (more,
+        # shorter plane iterations for a lattice this small)
+        wk3 = adjoint_ratio((128, 64, 64), 200, 20, variant=5)
+        best_fw = min(wk["forward_ms_per_step"], wk2["forward_ms_per_step"], wk3["forward_ms_per_step"])
+        best_bw = min(wk["backward_ms_per_step"], wk2["backward_ms_per_step"], wk3["backward_ms_per_step"])
         out["adjoint"] = {"workload": wk, "workload_two_array_single_reverse_steps": wk2,
+                          "workload_merged_16x16_tiles": wk3,
                           "workload_best_backward_over_best_forward": round(best_bw / best_fw, 3),
                           "bandwidth_bound": adjoint_ratio((256, 256, 256), 40, 20, reps=2),
                           # every other state kept (20 x 1.3 GB): no recompute in the backward

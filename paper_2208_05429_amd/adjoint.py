@@ -25,7 +25,7 @@ def _ptr(t):
 
 class ForceAdjoint(torch.autograd.Function):
     """u_T = ForceAdjoint.apply(F, f0, spec); spec = dict(shape, tau, storage,
-    faces, wall_u, steps, checkpoint[, merged])."""
+    faces, wall_u, steps, checkpoint[, merged, scheme, variant])."""
 
     @staticmethod
     def forward(ctx, F, f0, spec):
@@ -33,7 +33,8 @@ class ForceAdjoint(torch.autograd.Function):
         steps, k = int(spec["steps"]), int(spec["checkpoint"])
         lat = Lattice(shape, spec["tau"], storage, spec.get("scheme", "swap2"), spec["faces"],
                       spec.get("wall_u", (0.0, 0.0, 0.0)), force=F.detach(),
-                      f=torch.empty(f0.shape, dtype=f0.dtype, device=f0.device), velocities=f0.shape[0])
+                      f=torch.empty(f0.shape, dtype=f0.dtype, device=f0.device), velocities=f0.shape[0],
+                      variant=int(spec.get("variant", 0)))
         ckpts = [f0.detach().clone(memory_format=torch.contiguous_format)]
         t = 0
         while t < steps:

@@ -397,3 +397,46 @@ def test_tgv1024_fp64_merged_rounds_sampled_cells():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+
+
+# Kernel variant 5: 16 x 16 plain tiles of 448 threads (for lattices that
+# give the default tiles under half the device): bitwise equal to the
+# two-array kernel on ragged, walled and forced lattices, and in rounds
+# (6 x 272 x 1024: 17 x 64 tiles in bands of 4 tile rows, a short last band in
+# x segments of its own).
+SMALL_TILE_CASES = [
+    ((20, 37, 45), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, -0.02), False),
+    ((24, 30, 61), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
+    ((17, 41, 33), (PERIODIC,) * 6, (0.0, 0.0, 0.0), False),
+    ((12, 272, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0), False),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SMALL_TILE_CASES)))
+def test_small_tile_variant_matches_two_array_bitwise(case):
+    shape, faces, wall_u, with_force = SMALL_TILE_CASES[case]
+    names = [_NAMES[f] for f in faces]
+    rho0, u0 = wl.taylor_green_3d(shape, 0.03)
+    u0 = u0 + wl.uniform_noise(shape, 5e-3, 480 + case)
+    r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 481 + case)), torch.as_tensor(u0)
+    F = torch.as_tensor(wl.normal_field(shape, 1e-4, 482 + case), dtype=torch.float32) if with_force else None
+    print(f"[gpu] variant 5 (16 x 16 tiles) {shape} {names} force={with_force}", flush=True)
+    ref = Lattice(shape, 0.6, "f32", "two_array", names, wall_u, force=F, rho0=r0, u0=v0)
+    f0 = ref.f.clone()
+    ref.step(5)
+    for scheme in ("swap2", "swap1"):
+        lat = Lattice(shape, 0.6, "f32", scheme, names, wall_u, force=F, f=f0.clone(), variant=5)
+        lat.step(5)
+        torch.cuda.synchronize()
+        assert torch.equal(lat.f.view(torch.int32), ref.f.view(torch.int32)), scheme
+        lat.close()
+    for storage in ("f16", "bf16"):  # the 16-bit builds of the tile: in place = out of place
+        lat = Lattice(shape, 0.6, storage, "swap2", names, wall_u, force=F, rho0=r0, u0=v0, variant=5)
+        a, b = torch.empty_like(lat.f), torch.empty_like(lat.f)
+        lat.step_into(lat.f, a, 2)
+        lat.step_into(a, b, 2)
+        lat.step(4)
+        torch.cuda.synchronize()
+        assert torch.equal(lat.f.view(torch.int16), b.view(torch.int16)), storage
+        lat.close()
+    ref.close()

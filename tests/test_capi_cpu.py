@@ -74,6 +74,17 @@ def test_planes_of_4_gib_per_direction_are_rejected():
     assert _status(_cfg(shape=(1, 32768, 16384)))[0] == capi.LBM_OK                     # FP32, 2 GiB
 
 
+def test_variant_values_per_storage():
+    # variant 5 (16 x 16 plain tiles) is built for the 32- and 16-bit
+    # storages; FP64 has variants 0-2 only
+    for storage in (capi.LBM_F32, capi.LBM_F16_OFS, capi.LBM_BF16_OFS):
+        assert _status(_cfg(shape=(128, 64, 64), storage=storage, variant=5))[0] == capi.LBM_OK, storage
+    for v in (0, 1, 2):
+        assert _status(_cfg(shape=(128, 64, 64), storage=capi.LBM_F64, variant=v))[0] == capi.LBM_OK, v
+    assert _status(_cfg(shape=(128, 64, 64), storage=capi.LBM_F64, variant=5))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(shape=(128, 64, 64), variant=6))[0] == capi.LBM_EUNSUPPORTED
+
+
 def test_rounds_plan_for_large_planes():
     # 1024^2 planes need 1024 tiles of 16x64: four rounds of 256 tile rows' bands;
     # the work buffer holds 2 M boundary rows of every band for all x

@@ -143,9 +143,11 @@ constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1,
                                      {1, 16, 64, 512, 0, 1}, {2, 32, 32, 512, 1, 1}, {1, 32, 32, 512, 1, 1},
                                      {2, 32, 32, 512, 0, 1}, {1, 32, 32, 512, 0, 1}, {2, 16, 64, 512, 1, 2},
                                      {1, 16, 64, 512, 1, 2}, {2, 16, 16, 448, 0, 1}, {1, 16, 16, 448, 0, 1}};
-// Three merged steps (plain layout, FP32): one frame column per thread needs
-// (TY + 6) x (TZ + 6) <= 512; variant v of LBM_SWAP3 takes entry v.
-constexpr ShapeEntry kShapesM3F32[] = {{3, 10, 26, 512, 0, 1}, {3, 16, 16, 512, 0, 1}};
+// Three merged steps (plain layout, FP32; variant v of LBM_SWAP3 takes entry
+// v): 16 x 32 tiles with two frame columns per thread (a 22 x 38 frame, three
+// exchange levels in 139 KB of LDS; 512^3 43.7 GLUPS), then one column per
+// thread, (TY + 6) x (TZ + 6) <= 512, on 10 x 26 and 16 x 16 tiles (30.4).
+constexpr ShapeEntry kShapesM3F32[] = {{3, 16, 32, 512, 0, 1}, {3, 10, 26, 512, 0, 1}, {3, 16, 16, 512, 0, 1}};
 
 hipError_t launch_march_f64(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);
 hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s);

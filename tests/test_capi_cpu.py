@@ -165,7 +165,8 @@ def test_three_merged_steps_are_built_for_fp32_only():
     assert _status(_cfg(scheme=capi.LBM_SWAP3, variant=1))[0] == capi.LBM_OK
     for st in (capi.LBM_F64, capi.LBM_F16_OFS, capi.LBM_BF16_OFS):
         assert _status(_cfg(scheme=capi.LBM_SWAP3, storage=st))[0] == capi.LBM_EUNSUPPORTED
-    assert _status(_cfg(scheme=capi.LBM_SWAP3, variant=2))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(scheme=capi.LBM_SWAP3, variant=2))[0] == capi.LBM_OK
+    assert _status(_cfg(scheme=capi.LBM_SWAP3, variant=3))[0] == capi.LBM_EUNSUPPORTED
     assert _status(_cfg(scheme=4))[0] == capi.LBM_EINVAL
 
 

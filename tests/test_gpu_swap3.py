@@ -1,10 +1,10 @@
 """Three merged steps per pass (LBM_SWAP3, the deeper merging the paper's
-conclusion names as its next step; the plain one-column-per-thread layout,
+conclusion names as its next step; the plain layout with one or two columns per thread,
 FP32).  Every scheme runs the same per-cell arithmetic, so three merged steps
 must equal three plain two-array steps to the bit: any difference is a race,
 a missing halo cell or an indexing slip of the third level.  Covered: ragged
 tiles, walls, a moving lid, a body force, remainders of one and two steps,
-both compiled tile shapes, rounds over bands of tile rows, the full 512^3
+the three compiled tile shapes, rounds over bands of tile rows, the full 512^3
 lattice against the two-step kernel, and the FP64 oracle."""
 import numpy as np
 import pytest
@@ -50,7 +50,7 @@ def _agree(shape, faces, wall_u, steps_list, variant=0, force=None, seed=0):
     ref.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])  # 16 x 32 with two columns per thread; 10 x 26, 16 x 16
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_three_merged_steps_equal_two_array_bitwise(case, variant):
     shape, faces, wall_u = CASES[case]
@@ -65,13 +65,15 @@ def test_three_merged_steps_with_a_body_force():
            seed=513)
 
 
-@pytest.mark.parametrize("shape,faces,wall_u", [
-    ((6, 280, 290), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),  # 28 x 12 tiles, 2 rounds
-    ((5, 285, 266), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),  # periodic y with a 5-row last tile row
-    ((4, 512, 520), (WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.0, 0.0)),  # 16 x 16 tiles across the seam
+@pytest.mark.parametrize("shape,faces,wall_u,variant", [
+    ((6, 280, 290), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01), 1),  # 10 x 26: 28 x 12 tiles, 2 rounds
+    ((5, 285, 266), (PERIODIC,) * 6, (0.0, 0.0, 0.0), 1),  # periodic y with a 5-row last tile row
+    ((4, 512, 520), (WALL, WALL, PERIODIC, PERIODIC, WALL, WALL), (0.0, 0.0, 0.0), 2),  # 16 x 16 tiles across the seam
+    # 16 x 32 tiles, two columns per thread: 17 x 32 tiles in bands of 8, 8 and 1 tile rows
+    ((6, 272, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0), 0),
 ])
-def test_three_merged_steps_in_rounds_equal_two_array_bitwise(shape, faces, wall_u):
-    _agree(shape, faces, wall_u, (3, 4), seed=520)
+def test_three_merged_steps_in_rounds_equal_two_array_bitwise(shape, faces, wall_u, variant):
+    _agree(shape, faces, wall_u, (3, 4), variant=variant, seed=520)
 
 
 def test_three_merged_steps_match_the_oracle():
@@ -90,8 +92,8 @@ def test_three_merged_steps_match_the_oracle():
 
 
 def test_three_merged_steps_at_512_cubed_equal_two_steps_bitwise():
-    # the 512^3 Taylor-Green workload (16 x 16 tiles in four rounds) against
-    # the two-step kernel of the bench, 6 steps each
+    # the 512^3 Taylor-Green workload (16 x 32 tiles, two columns per thread,
+    # in two rounds) against the two-step kernel of the bench, 6 steps each
     shape = (512, 512, 512)
     u0 = wl.taylor_green_3d_device(shape, 0.02, (0.0, 0.0, 0.0), "cuda")
     a = Lattice(shape, 0.6, "f32", "swap3", u0=u0)

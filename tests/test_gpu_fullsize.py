@@ -363,6 +363,34 @@ def test_tgv1024_fp32_merged_rounds_sampled_cells():
     torch.cuda.empty_cache()
 
 
+def test_tgv512_fp64_merged_short_last_band_sampled_cells():
+    # FP64 512^3 on 10 x 32 tiles: 52 x 16 tiles in bands of 16, 16, 16 and 4
+    # tile rows (rows 0-159, 160-319, 320-479, 480-511); the short last band
+    # marches in 4 x segments of 128 planes of its own.  Sampled cells at the
+    # band seams, the last band's segment seams, the x wrap and at random.
+    cfg = wl.TGV_512
+    shape, tau, n = cfg["shape"], cfg["tau"], 4
+    print(f"[gpu] 512^3 f64 swap2 rounds with a segmented last band, {n} steps", flush=True)
+    _, u0 = wl.tgv_512_fields(shape)
+    lat = Lattice(shape, tau, "f64", "swap2", u0=torch.from_numpy(u0))
+    s0 = lat.sums()
+    lat.step(n)
+    torch.cuda.synchronize()
+    s1 = lat.sums()
+    cells = [(0, 159, 0), (1, 160, 31), (200, 319, 32), (300, 320, 511), (5, 479, 63), (6, 480, 64),
+             (127, 490, 100), (128, 500, 101), (255, 511, 7), (256, 485, 300), (383, 495, 301), (384, 505, 0),
+             (511, 511, 511), (0, 0, 1)] + wl.sample_cells(shape, 8, 15)
+    got = gpu_cells(lat, cells)
+    for c, g in zip(cells, got):
+        ref = oracle_center(None, u0, shape, (PERIODIC,) * 6, (0, 0, 0), tau, c, n)
+        assert np.abs(g - ref).max() <= 1e-13, c
+    assert abs(s1[0] - s0[0]) <= 1e-12 * s0[0]
+    assert np.abs(s1[1:] - s0[1:]).max() <= 1e-12 * s0[0]
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
 def test_tgv1024_fp64_merged_rounds_sampled_cells():
     # 1024^3 in FP64: 163 GB of distributions, which fit the 288 GB of HBM only
     # as a single copy (two arrays would need 326 GB); 13 rounds of bands of

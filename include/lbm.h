@@ -97,8 +97,8 @@ typedef struct {
     int32_t use_force;  /* 1: a body-force density field F (3N, double for LBM_F64, float otherwise) */
     int32_t variant;    /* 0 = default kernel shape; other values select alternative compiled tile shapes
                            (e.g. D3Q19 FP64: 0 = 10x32 tiles, 1 = 12x28, 2 = 10x32 with loads two planes
-                           ahead; D3Q19 32/16-bit: 5 = 16x16 tiles for small lattices); LBM_EUNSUPPORTED for
-                           a value with no compiled shape */
+                           ahead; D3Q19 32/16-bit: 5 = 16x16 tiles for small lattices, 6 = 12x28 plain
+                           tiles); LBM_EUNSUPPORTED for a value with no compiled shape */
     int32_t velocities; /* velocity set: 0 or 19 = D3Q19 (the paper's); 15 = D3Q15, 27 = D3Q27 (Sec. 4.1 names
                            both as sets the two-step rule holds for): every storage (16-bit: the default
                            tiles), LBM_TWO_ARRAY, LBM_SWAP1 and LBM_SWAP2 (large planes in rounds), the adjoint;

@@ -3,7 +3,7 @@
 
 namespace lbm {
 
-using List_bf16 = ShapeList<PRShape<ST_BF16, 2, 16, 64, true>, PRShape<ST_BF16, 1, 16, 64, true>, Shape<ST_BF16, 2, 16, 64, 512, true>, Shape<ST_BF16, 1, 16, 64, 512, true>, PRShape<ST_BF16, 2, 32, 32, true>, PRShape<ST_BF16, 1, 32, 32, true>, Shape<ST_BF16, 2, 32, 32, 512, true>, Shape<ST_BF16, 1, 32, 32, 512, true>, PRShape<ST_BF16, 2, 16, 64, true, 2>, PRShape<ST_BF16, 1, 16, 64, true, 2>, Shape<ST_BF16, 2, 16, 16, 448, true>, Shape<ST_BF16, 1, 16, 16, 448, true>>;
+using List_bf16 = ShapeList<PRShape<ST_BF16, 2, 16, 64, true>, PRShape<ST_BF16, 1, 16, 64, true>, Shape<ST_BF16, 2, 16, 64, 512, true>, Shape<ST_BF16, 1, 16, 64, 512, true>, PRShape<ST_BF16, 2, 32, 32, true>, PRShape<ST_BF16, 1, 32, 32, true>, Shape<ST_BF16, 2, 32, 32, 512, true>, Shape<ST_BF16, 1, 32, 32, 512, true>, PRShape<ST_BF16, 2, 16, 64, true, 2>, PRShape<ST_BF16, 1, 16, 64, true, 2>, Shape<ST_BF16, 2, 16, 16, 448, true>, Shape<ST_BF16, 1, 16, 16, 448, true>, Shape<ST_BF16, 2, 12, 28, 512, true>, Shape<ST_BF16, 1, 14, 30, 512, true>>;
 
 hipError_t launch_march_bf16(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
 {

@@ -135,14 +135,17 @@ constexpr ShapeEntry kShapesF64[] = {{2, 10, 32, 512, 0, 1}, {1, 12, 34, 512, 0,
                                      {2, 10, 32, 512, 0, 2}, {1, 12, 34, 512, 0, 2}};
 // 32- and 16-bit storage (variant v takes entries 2v and 2v+1): 16 x 64
 // pair-and-ring tiles; the plain layout of 16 x 64; 32 x 32 pair-and-ring and
-// plain; 16 x 64 pair-and-ring with loads two planes ahead; and 16 x 16 plain
+// plain; 16 x 64 pair-and-ring with loads two planes ahead; 16 x 16 plain
 // tiles of 448 threads for lattices that give the others under half the
 // device's workgroups (128 x 64 x 64 channel with walls and a force: 41.7
-// against 70.0 us per step; slower from 128^3 up).
+// against 70.0 us per step; slower from 128^3 up); and 12 x 28 plain tiles,
+// whose 12-row height also serves planes in rounds across a periodic y seam
+// where every 16-row multiple would leave a last row thinner than the halo.
 constexpr ShapeEntry kShapesF32[] = {{2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}, {2, 16, 64, 512, 0, 1},
                                      {1, 16, 64, 512, 0, 1}, {2, 32, 32, 512, 1, 1}, {1, 32, 32, 512, 1, 1},
                                      {2, 32, 32, 512, 0, 1}, {1, 32, 32, 512, 0, 1}, {2, 16, 64, 512, 1, 2},
-                                     {1, 16, 64, 512, 1, 2}, {2, 16, 16, 448, 0, 1}, {1, 16, 16, 448, 0, 1}};
+                                     {1, 16, 64, 512, 1, 2}, {2, 16, 16, 448, 0, 1}, {1, 16, 16, 448, 0, 1},
+                                     {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}};
 // Three merged steps (plain layout, FP32; variant v of LBM_SWAP3 takes entry
 // v): 16 x 32 tiles with two frame columns per thread (a 22 x 38 frame, three
 // exchange levels in 139 KB of LDS; 512^3 43.7 GLUPS), then one column per

@@ -3,7 +3,7 @@
 
 namespace lbm {
 
-using List_f32 = ShapeList<PRShape<ST_F32, 2, 16, 64, true>, PRShape<ST_F32, 1, 16, 64, true>, Shape<ST_F32, 2, 16, 64, 512, true>, Shape<ST_F32, 1, 16, 64, 512, true>, PRShape<ST_F32, 2, 32, 32, true>, PRShape<ST_F32, 1, 32, 32, true>, Shape<ST_F32, 2, 32, 32, 512, true>, Shape<ST_F32, 1, 32, 32, 512, true>, PRShape<ST_F32, 2, 16, 64, true, 2>, PRShape<ST_F32, 1, 16, 64, true, 2>, Shape<ST_F32, 3, 10, 26, 512, true>, Shape<ST_F32, 3, 16, 16, 512, true>, Shape<ST_F32, 3, 16, 32, 512, true>, Shape<ST_F32, 2, 16, 16, 448, true>, Shape<ST_F32, 1, 16, 16, 448, true>>;
+using List_f32 = ShapeList<PRShape<ST_F32, 2, 16, 64, true>, PRShape<ST_F32, 1, 16, 64, true>, Shape<ST_F32, 2, 16, 64, 512, true>, Shape<ST_F32, 1, 16, 64, 512, true>, PRShape<ST_F32, 2, 32, 32, true>, PRShape<ST_F32, 1, 32, 32, true>, Shape<ST_F32, 2, 32, 32, 512, true>, Shape<ST_F32, 1, 32, 32, 512, true>, PRShape<ST_F32, 2, 16, 64, true, 2>, PRShape<ST_F32, 1, 16, 64, true, 2>, Shape<ST_F32, 3, 10, 26, 512, true>, Shape<ST_F32, 3, 16, 16, 512, true>, Shape<ST_F32, 3, 16, 32, 512, true>, Shape<ST_F32, 2, 16, 16, 448, true>, Shape<ST_F32, 1, 16, 16, 448, true>, Shape<ST_F32, 2, 12, 28, 512, true>, Shape<ST_F32, 1, 14, 30, 512, true>>;
 
 hipError_t launch_march_f32(bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
 {

@@ -41,10 +41,11 @@ def _status(cfg):
     (dict(faces=(3, 3, 0, 0, 0, 0)), capi.LBM_EINVAL),
     (dict(variant=99), capi.LBM_EUNSUPPORTED),
     # rounds across a periodic y seam: a last tile row thinner than the halo for
-    # every tile height built (16 and 32 rows)
-    (dict(shape=(64, 1025, 1024)), capi.LBM_EUNSUPPORTED),
+    # every tile height built (16, 32 and 12 rows: 1057 = 66 x 16 + 1 = 33 x 32 + 1
+    # = 88 x 12 + 1)
+    (dict(shape=(64, 1057, 1024)), capi.LBM_EUNSUPPORTED),
     # the same with odd nz (plain layout only)
-    (dict(shape=(64, 1025, 1023)), capi.LBM_EUNSUPPORTED),
+    (dict(shape=(64, 1057, 1023)), capi.LBM_EUNSUPPORTED),
     # FP64 across a periodic y seam: a last tile row thinner than the halo for both
     # tile heights built (121 = 12 x 10 + 1 = 10 x 12 + 1)
     (dict(shape=(64, 121, 1024), storage=capi.LBM_F64), capi.LBM_EUNSUPPORTED),
@@ -82,7 +83,8 @@ def test_variant_values_per_storage():
     for v in (0, 1, 2):
         assert _status(_cfg(shape=(128, 64, 64), storage=capi.LBM_F64, variant=v))[0] == capi.LBM_OK, v
     assert _status(_cfg(shape=(128, 64, 64), storage=capi.LBM_F64, variant=5))[0] == capi.LBM_EUNSUPPORTED
-    assert _status(_cfg(shape=(128, 64, 64), variant=6))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(shape=(128, 64, 64), variant=6))[0] == capi.LBM_OK  # 12 x 28 plain tiles
+    assert _status(_cfg(shape=(128, 64, 64), variant=7))[0] == capi.LBM_EUNSUPPORTED
 
 
 def test_rounds_plan_for_large_planes():
@@ -100,6 +102,9 @@ def test_rounds_plan_for_large_planes():
     # and one thinner than the halo another tile height (1009 = 31 x 32 + 17)
     assert _status(_cfg(shape=(nx, 1000, 1024)))[0] == capi.LBM_OK
     assert _status(_cfg(shape=(nx, 1009, 1024)))[0] == capi.LBM_OK
+    # 1025 rows: 16- and 32-row tiles leave one row, the 12-row plain tile five
+    assert _status(_cfg(shape=(nx, 1025, 1024)))[0] == capi.LBM_OK
+    assert _status(_cfg(shape=(nx, 1025, 1023)))[0] == capi.LBM_OK
     # FP64 (plain layout, 10 x 32 tiles): 103 x 32 tiles, bands of 8 tile rows
     # (256 // 32), 13 rounds, each band's 2 M boundary rows saved, and the side
     # planes of one x segment; variant 1 (12 x 28 tiles): 86 x 37 tiles, bands

@@ -162,6 +162,10 @@ BANDED_CASES = [
     ((24, 280, 1030), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, 0.01)),
     # and in the plain layout (odd nz; last band 3 x 16 tiles, 5 segments)
     ((20, 304, 1001), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    # 1025 rows across the periodic seam: 16- and 32-row tiles would leave one
+    # row, so 12 x 28 plain tiles (a 5-row last tile row), even and odd nz
+    ((4, 1025, 1024), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
+    ((3, 1025, 1023), (PERIODIC,) * 6, (0.0, 0.0, 0.0)),
 ]
 _NAMES = {PERIODIC: "periodic", WALL: "wall", MOVING_WALL: "moving"}
 
@@ -427,11 +431,12 @@ def test_tgv1024_fp64_merged_rounds_sampled_cells():
     torch.cuda.empty_cache()
 
 
-# Kernel variant 5: 16 x 16 plain tiles of 448 threads (for lattices that
-# give the default tiles under half the device): bitwise equal to the
-# two-array kernel on ragged, walled and forced lattices, and in rounds
-# (6 x 272 x 1024: 17 x 64 tiles in bands of 4 tile rows, a short last band in
-# x segments of its own).
+# Kernel variants 5 (16 x 16 plain tiles of 448 threads, for lattices that
+# give the default tiles under half the device) and 6 (12 x 28 plain tiles):
+# bitwise equal to the two-array kernel on ragged, walled and forced
+# lattices, and in rounds (12 x 272 x 1024: 17 x 64 tiles of 16 x 16 in bands
+# of 4 tile rows, a short last band in x segments of its own; 23 x 37 of
+# 12 x 28 in bands of 6).
 SMALL_TILE_CASES = [
     ((20, 37, 45), (WALL, WALL, WALL, MOVING_WALL, WALL, WALL), (0.05, 0.0, -0.02), False),
     ((24, 30, 61), (PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0), True),
@@ -440,26 +445,27 @@ SMALL_TILE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("variant", [5, 6])  # 16 x 16 tiles of 448 threads; 12 x 28 plain tiles
 @pytest.mark.parametrize("case", range(len(SMALL_TILE_CASES)))
-def test_small_tile_variant_matches_two_array_bitwise(case):
+def test_small_tile_variant_matches_two_array_bitwise(case, variant):
     shape, faces, wall_u, with_force = SMALL_TILE_CASES[case]
     names = [_NAMES[f] for f in faces]
     rho0, u0 = wl.taylor_green_3d(shape, 0.03)
     u0 = u0 + wl.uniform_noise(shape, 5e-3, 480 + case)
     r0, v0 = torch.as_tensor(wl.random_density(shape, 0.01, 481 + case)), torch.as_tensor(u0)
     F = torch.as_tensor(wl.normal_field(shape, 1e-4, 482 + case), dtype=torch.float32) if with_force else None
-    print(f"[gpu] variant 5 (16 x 16 tiles) {shape} {names} force={with_force}", flush=True)
+    print(f"[gpu] variant {variant} {shape} {names} force={with_force}", flush=True)
     ref = Lattice(shape, 0.6, "f32", "two_array", names, wall_u, force=F, rho0=r0, u0=v0)
     f0 = ref.f.clone()
     ref.step(5)
     for scheme in ("swap2", "swap1"):
-        lat = Lattice(shape, 0.6, "f32", scheme, names, wall_u, force=F, f=f0.clone(), variant=5)
+        lat = Lattice(shape, 0.6, "f32", scheme, names, wall_u, force=F, f=f0.clone(), variant=variant)
         lat.step(5)
         torch.cuda.synchronize()
         assert torch.equal(lat.f.view(torch.int32), ref.f.view(torch.int32)), scheme
         lat.close()
     for storage in ("f16", "bf16"):  # the 16-bit builds of the tile: in place = out of place
-        lat = Lattice(shape, 0.6, storage, "swap2", names, wall_u, force=F, rho0=r0, u0=v0, variant=5)
+        lat = Lattice(shape, 0.6, storage, "swap2", names, wall_u, force=F, rho0=r0, u0=v0, variant=variant)
         a, b = torch.empty_like(lat.f), torch.empty_like(lat.f)
         lat.step_into(lat.f, a, 2)
         lat.step_into(a, b, 2)

@@ -29,6 +29,7 @@ constexpr SetShapes kSetShapes[] = {
     {27, ST_F32, 1, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
     {27, ST_F64, 0, {2, 8, 32, 448, 0, 1}, {1, 10, 32, 448, 0, 1}},  // whole cache-line rows; 256 tiles of 256^2
     {27, ST_F64, 1, {2, 8, 24, 384, 0, 1}, {1, 10, 26, 384, 0, 1}},
+    {27, ST_F64, 2, {2, 10, 26, 448, 0, 1}, {1, 10, 26, 384, 0, 1}},  // a 10-row height for periodic y seams
     // FP16/BF16 offset storage: the default tiles of FP32 (and the plain
     // 16 x 64 tile that D3Q15 takes for odd nz)
     {15, ST_F16, 0, {2, 16, 64, 512, 1, 1}, {1, 16, 64, 512, 1, 1}},

@@ -9,7 +9,8 @@ namespace lbm {
 using List_q27_f32 = ShapeList<SetShape<D3Q27, ST_F32, 2, 12, 28, 512>, SetShape<D3Q27, ST_F32, 1, 14, 30, 512>,
                                SetShape<D3Q27, ST_F32, 2, 16, 32, 512>, SetShape<D3Q27, ST_F32, 1, 16, 32, 512>>;
 using List_q27_f64 = ShapeList<SetShape<D3Q27, ST_F64, 2, 8, 24, 384>, SetShape<D3Q27, ST_F64, 1, 10, 26, 384>,
-                               SetShape<D3Q27, ST_F64, 2, 8, 32, 448>, SetShape<D3Q27, ST_F64, 1, 10, 32, 448>>;
+                               SetShape<D3Q27, ST_F64, 2, 8, 32, 448>, SetShape<D3Q27, ST_F64, 1, 10, 32, 448>,
+                               SetShape<D3Q27, ST_F64, 2, 10, 26, 448>>;
 
 hipError_t launch_march_q27(int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a, hipStream_t s)
 {

@@ -87,6 +87,18 @@ def test_variant_values_per_storage():
     assert _status(_cfg(shape=(128, 64, 64), variant=7))[0] == capi.LBM_EUNSUPPORTED
 
 
+def test_d3q27_fp64_rounds_across_a_periodic_seam():
+    # D3Q27 in FP64 tiles 8 rows high (8 x 32, 8 x 24); across a periodic y
+    # seam in rounds a last row of one would be thinner than the halo, so the
+    # planner takes the 10-row tile (10 x 26): 257 rows run, 281 (= 35 x 8 + 1
+    # = 28 x 10 + 1) do not
+    q27 = dict(storage=capi.LBM_F64, velocities=27)
+    assert _status(_cfg(shape=(32, 257, 256), **q27))[0] == capi.LBM_OK
+    assert _status(_cfg(shape=(32, 281, 256), **q27))[0] == capi.LBM_EUNSUPPORTED
+    assert _status(_cfg(shape=(32, 257, 256), variant=2, **q27))[0] == capi.LBM_OK
+    assert _status(_cfg(shape=(32, 257, 256), variant=3, **q27))[0] == capi.LBM_EUNSUPPORTED
+
+
 def test_rounds_plan_for_large_planes():
     # 1024^2 planes need 1024 tiles of 16x64: four rounds of 256 tile rows' bands;
     # the work buffer holds 2 M boundary rows of every band for all x

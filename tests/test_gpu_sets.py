@@ -361,3 +361,25 @@ def test_sets_1024_cubed_fp32_merged_rounds_sampled_cells(q):
     lat.close()
     del lat
     torch.cuda.empty_cache()
+
+
+def test_d3q27_fp64_rounds_across_a_periodic_seam_equal_two_array_bitwise():
+    # 257 rows: tiles 8 rows high would leave one row across the periodic seam,
+    # so the plane runs 10 x 26 tiles (26 x 10 tiles, 2 rounds, a 7-row last
+    # tile row)
+    shape, faces = (4, 257, 256), (PERIODIC,) * 6
+    rho0, u0 = _init(shape, 780)
+    names = [NAMES[f] for f in faces]
+    print(f"[gpu] D3Q27 f64 rounds across the seam {shape}", flush=True)
+    ref = Lattice(shape, 0.7, "f64", "two_array", names, (0.0, 0.0, 0.0), None, torch.as_tensor(rho0),
+                  torch.as_tensor(u0), velocities=27)
+    for scheme in ("swap2", "swap1"):
+        lat = Lattice(shape, 0.7, "f64", scheme, names, (0.0, 0.0, 0.0), f=ref.f.clone(), velocities=27)
+        r = Lattice(shape, 0.7, "f64", "two_array", names, (0.0, 0.0, 0.0), f=ref.f.clone(), velocities=27)
+        lat.step(5)
+        r.step(5)
+        torch.cuda.synchronize()
+        assert torch.equal(lat.f.view(torch.int64), r.f.view(torch.int64)), scheme
+        lat.close()
+        r.close()
+    ref.close()

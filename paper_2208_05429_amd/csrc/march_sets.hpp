@@ -38,6 +38,11 @@ constexpr SetShapes kSetShapes[] = {
     {15, ST_BF16, 1, {2, 16, 64, 512, 0, 1}, {1, 16, 64, 512, 0, 1}},
     {27, ST_F16, 0, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},
     {27, ST_BF16, 0, {2, 16, 32, 512, 0, 1}, {1, 16, 32, 512, 0, 1}},
+    // a 12-row height, for planes in rounds across a periodic y seam
+    {15, ST_F16, 2, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
+    {15, ST_BF16, 2, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
+    {27, ST_F16, 1, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
+    {27, ST_BF16, 1, {2, 12, 28, 512, 0, 1}, {1, 14, 30, 512, 0, 1}},
 };
 hipError_t launch_march_set(int lat, int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a,
                             hipStream_t s);

@@ -7,9 +7,11 @@ namespace lbm {
 
 template <int S>
 using List_q15_16 = ShapeList<PRSetShape<D3Q15, S, 2, 16, 64>, PRSetShape<D3Q15, S, 1, 16, 64>,
-                              SetShape<D3Q15, S, 2, 16, 64, 512>, SetShape<D3Q15, S, 1, 16, 64, 512>>;
+                              SetShape<D3Q15, S, 2, 16, 64, 512>, SetShape<D3Q15, S, 1, 16, 64, 512>,
+                              SetShape<D3Q15, S, 2, 12, 28, 512>, SetShape<D3Q15, S, 1, 14, 30, 512>>;
 template <int S>
-using List_q27_16 = ShapeList<SetShape<D3Q27, S, 2, 16, 32, 512>, SetShape<D3Q27, S, 1, 16, 32, 512>>;
+using List_q27_16 = ShapeList<SetShape<D3Q27, S, 2, 16, 32, 512>, SetShape<D3Q27, S, 1, 16, 32, 512>,
+                              SetShape<D3Q27, S, 2, 12, 28, 512>, SetShape<D3Q27, S, 1, 14, 30, 512>>;
 
 hipError_t launch_march_set16(int lat, int storage, bool walls, bool force, const MarchPlan& p, const MarchArgs& a,
                               hipStream_t s)

@@ -193,9 +193,14 @@ def test_velocity_sets_sizes_and_limits():
             st, fb, wb = _status(_cfg(storage=storage, velocities=q))
             assert st == capi.LBM_OK and fb == q * 32 ** 3 * s
     assert _status(_cfg(velocities=0))[1] == 19 * 32 ** 3 * 4  # 0 is D3Q19
-    for q in (15, 27):
-        # 16-bit storage takes the default tiles only (and D3Q15's plain 16 x 64 as variant 1)
-        assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q, variant=2))[0] == capi.LBM_EUNSUPPORTED
+    for q, last in ((15, 2), (27, 1)):
+        # 16-bit storage: the default tiles, D3Q15's plain 16 x 64 as variant 1,
+        # and 12 x 28 plain tiles (a second tile height across a periodic seam)
+        assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q, variant=last))[0] == capi.LBM_OK
+        assert _status(_cfg(storage=capi.LBM_F16_OFS, velocities=q, variant=last + 1))[0] == capi.LBM_EUNSUPPORTED
+        # across a periodic y seam in rounds 16-row tiles would leave one row of
+        # 1025; the 12-row tiles leave five
+        assert _status(_cfg(shape=(8, 1025, 1024), storage=capi.LBM_BF16_OFS, velocities=q))[0] == capi.LBM_OK
         assert _status(_cfg(scheme=capi.LBM_SWAP3, velocities=q))[0] == capi.LBM_EUNSUPPORTED
         assert _status(_cfg(velocities=q, variant=4))[0] == capi.LBM_EUNSUPPORTED
     # a plane of more tiles than co-resident workgroups runs in rounds: the

@@ -383,3 +383,22 @@ def test_d3q27_fp64_rounds_across_a_periodic_seam_equal_two_array_bitwise():
         lat.close()
         r.close()
     ref.close()
+
+
+@pytest.mark.parametrize("q", [15, 27])
+def test_sets_16bit_rounds_across_a_periodic_seam_in_place_matches_out_of_place(q):
+    # 16-bit sets on a 1025-row periodic plane in rounds: 16-row tiles would
+    # leave a last row of one across the seam, so the plane takes 12 x 28 tiles
+    # (a 5-row last tile row); in place equal to out of place to the bit
+    shape = (4, 1025, 1024)
+    rho0, u0 = _init(shape, 790 + q)
+    print(f"[gpu] D3Q{q} bf16 rounds across the seam {shape}", flush=True)
+    lat = Lattice(shape, 0.6, "bf16", "swap2", ["periodic"] * 6, (0.0, 0.0, 0.0), rho0=torch.as_tensor(rho0),
+                  u0=torch.as_tensor(u0), velocities=q)
+    a, b = torch.empty_like(lat.f), torch.empty_like(lat.f)
+    lat.step_into(lat.f, a, 2)
+    lat.step_into(a, b, 2)
+    lat.step(4)
+    torch.cuda.synchronize()
+    assert torch.equal(lat.f.view(torch.int16), b.view(torch.int16))
+    lat.close()

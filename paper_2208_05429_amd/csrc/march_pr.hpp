@@ -640,6 +640,14 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
 #pragma unroll
             for (int k = 0; k < K; ++k) asm volatile("" : "+v"(byz[k]));
         }
+        if constexpr (WALLS && FORCE) {
+            // With a force as well, the LDS addresses derived from the column
+            // indices are hoisted the same way and spill (reloads that queue
+            // behind the plane's loads); rebuilding them per plane is cheaper.
+            asm volatile("" : "+v"(ci[0]), "+v"(ci[2]), "+v"(ci2[0]), "+v"(ci2[2]));
+            ci[1] = ci[0] + 1;
+            ci2[1] = ci2[0] + 1;
+        }
         R* X1w = X1[(M == 1) ? (i & 1) : 0];
         const int r_out = xl - M;
         const bool storing = r_out >= s && r_out < e;

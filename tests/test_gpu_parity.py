@@ -219,6 +219,29 @@ def test_force_periodic_pair_layout():
         assert rel(lat.distributions(), ref) <= 2e-6, scheme
 
 
+@pytest.mark.parametrize("faces,wall_u", [
+    ((PERIODIC, PERIODIC, WALL, WALL, WALL, WALL), (0.0, 0.0, 0.0)),
+    ((PERIODIC, PERIODIC, WALL, MOVING_WALL, WALL, WALL), (0.04, 0.0, -0.01)),
+])
+def test_walls_and_force_pair_layout_match_two_array_bitwise(faces, wall_u):
+    # walls in y and z with a body force on the pair-and-ring FP32 kernels
+    # (16 x 64 and 32 x 32 tiles, one and two merged steps): three tile rows and
+    # three tile columns with ragged last ones, against the two-array kernel;
+    # the oracle fixes the two-array result
+    shape = (10, 40, 150)
+    rho0, u0 = _noisy_init(shape, 320)
+    F = wl.normal_field(shape, 1e-4, 321)
+    o = Oracle(shape, 0.8, faces=faces, wall_u=wall_u)
+    ref = o.run(o.init(rho0, u0), 5, F)
+    lat, _, _, _ = gpu_run(shape, 0.8, "f32", "two_array", faces, wall_u, rho0, u0, F=F, steps=5)
+    assert rel(lat.distributions(), ref) <= 2e-6
+    a = lat.f.cpu().numpy().view(np.uint32)
+    for variant in (0, 2):
+        for scheme in ("swap1", "swap2"):
+            lat, _, _, _ = gpu_run(shape, 0.8, "f32", scheme, faces, wall_u, rho0, u0, F=F, steps=5, variant=variant)
+            assert np.array_equal(lat.f.cpu().numpy().view(np.uint32), a), (scheme, variant)
+
+
 def test_conservation_sums_match_oracle():
     shape = (20, 37, 45)
     faces, wall_u = CASES[0][1], CASES[0][2]

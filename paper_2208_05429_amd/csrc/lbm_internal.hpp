@@ -68,6 +68,7 @@ struct MarchArgs {
     // and a bias added to the progress a wait requires (0; a test hook sets an
     // unreachable one so that every wait gives up)
     int spin_limit, need_bias;
+    int nt_store;  // 1: the in-place stores of the pair-and-ring march are non-temporal
 };
 
 // One merged two-step adjoint pass (out of place).

@@ -51,13 +51,15 @@ struct Buf2<float> {
     {
         return K == 0 ? p.a : p.b;
     }
+    // AUX: the store's cache policy (0, or 2 for non-temporal)
+    template <int AUX = 0>
     static __device__ __forceinline__ void st(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t off)
     {
         typedef unsigned int u2 __attribute__((ext_vector_type(2)));
         u2 w;
         w[0] = __float_as_uint(a);
         w[1] = __float_as_uint(b);
-        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, AUX);
     }
 };
 template <>
@@ -74,9 +76,10 @@ struct Buf2<uint16_t> {
         return K == 0 ? uint16_t(p & 0xffffu) : uint16_t(p >> 16);
     }
     // both codes already packed (Codec::enc2)
+    template <int AUX = 0>
     static __device__ __forceinline__ void st(uint32_t w, __amdgpu_buffer_rsrc_t r, uint32_t off)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(w, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(w, r, off, 0, AUX);
     }
 };
 
@@ -576,17 +579,27 @@ __global__ __launch_bounds__(TY * TZ / 2) void k_march_pr(MarchArgs a)
         if (!__all(ok) && (tid & 63) == 0) __hip_atomic_fetch_or(a.flags, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
+    // Stores marked non-temporal keep the finished planes, which this pass
+    // does not read again, from displacing the halo and force lines other
+    // tiles are about to read from L2 (the planner's choice, uniform per launch).
     auto store_pair = [&](const R (&v0)[QL], const R (&v1)[QL], int r, bool live) {
         const T* bq = fo + (long long)(live ? r : 0) * PL;
         const uint32_t range = live ? plane_bytes : 0u;
+        auto all = [&](auto auxc) {
+            constexpr int AUX = decltype(auxc)::value;
 #pragma unroll
-        for (int q = 0; q < QL; ++q) {
-            if constexpr (sizeof(T) == 2)
-                Buf2<T>::st(Cd::enc2(v0[q], v1[q]), make_rsrc(bq, range), soffP);
-            else
-                Buf2<T>::st(v0[q], v1[q], make_rsrc(bq, range), soffP);
-            bq += N;
-        }
+            for (int q = 0; q < QL; ++q) {
+                if constexpr (sizeof(T) == 2)
+                    Buf2<T>::template st<AUX>(Cd::enc2(v0[q], v1[q]), make_rsrc(bq, range), soffP);
+                else
+                    Buf2<T>::template st<AUX>(v0[q], v1[q], make_rsrc(bq, range), soffP);
+                bq += N;
+            }
+        };
+        if (a.nt_store)
+            all(std::integral_constant<int, 2>{});
+        else
+            all(std::integral_constant<int, 0>{});
     };
 
     // step-1 collide of column k from its raw values (decoded here)
